@@ -1,0 +1,533 @@
+/*
+ * wilson_oracle.c -- plain FP64 CPU oracle for the Wilson-Dirac operator and
+ * its Krylov solves.
+ *
+ * TEST INFRASTRUCTURE ONLY. The tests, the smoke check and the benchmark's
+ * CPU-baseline leg call this library; the product (the HIP library and its
+ * Python binding) never does. It shares no code with the HIP path.
+ *
+ * The paper (Sec. 3) names the objects only: the fermion matrix M of Wilson
+ * fermions, its non-diagonal part ("dslash"), even-odd preconditioning, and the
+ * inversion M^-1 b for point sources b(x0) (Sec. 4, Eq. 1). Everything below is
+ * the textbook definition written out with no blocking, fusion or reordering:
+ *
+ *   D_W psi(x) = sum_mu [ f_mu(x) (1 - gamma_mu) U_mu(x)        psi(x+mu)
+ *                       + b_mu(x) (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *   M = 1 - kappa D_W,          M^dag = gamma5 M gamma5,
+ *
+ * with neighbours taken modulo the extents, f_mu(x) = phase_mu when the forward
+ * hop wraps (x_mu = L_mu - 1), b_mu(x) = conj(phase_mu) when the backward hop
+ * wraps (x_mu = 0), and 1 otherwise. Gamma matrices are explicit 4x4 complex
+ * matrices in the Euclidean chiral basis; spin and colour are multiplied out in
+ * full (no projection to half spinors).
+ *
+ * Layouts: complex128, site s = x + Lx*(y + Ly*(z + Lz*t));
+ *   U[s][mu][a][b]  (link on the bond s -> s+mu),   psi[s][spin][colour].
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double _Complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* Dirac matrices (Euclidean, Hermitian, chiral basis):                      */
+/*   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]  (k = x, y, z)              */
+/*   gamma_t = [[0, 1], [1, 0]]                                              */
+/*   gamma_5 = gamma_x gamma_y gamma_z gamma_t  ( = diag(1, 1, -1, -1) )     */
+/* ------------------------------------------------------------------------ */
+static cplx GAM[4][4][4];
+static cplx GAM5[4][4];
+
+static void matmul4(const cplx a[4][4], const cplx b[4][4], cplx c[4][4])
+{
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 4; ++k) s += a[i][k] * b[k][j];
+            c[i][j] = s;
+        }
+}
+
+__attribute__((constructor)) static void build_gammas(void)
+{
+    cplx sigma[3][2][2];
+    memset(sigma, 0, sizeof sigma);
+    sigma[0][0][1] = 1;  sigma[0][1][0] = 1;            /* sigma_1 */
+    sigma[1][0][1] = -I; sigma[1][1][0] = I;            /* sigma_2 */
+    sigma[2][0][0] = 1;  sigma[2][1][1] = -1;           /* sigma_3 */
+
+    memset(GAM, 0, sizeof GAM);
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                GAM[k][a][2 + b] = -I * sigma[k][a][b];
+                GAM[k][2 + a][b] = I * sigma[k][a][b];
+            }
+    for (int a = 0; a < 2; ++a) {
+        GAM[3][a][2 + a] = 1;
+        GAM[3][2 + a][a] = 1;
+    }
+    cplx t1[4][4], t2[4][4];
+    matmul4(GAM[0], GAM[1], t1);
+    matmul4(t1, GAM[2], t2);
+    matmul4(t2, GAM[3], GAM5);
+}
+
+/* Copy out the oracle's Dirac matrices: mu = 0..3 for gamma_mu, 4 for gamma_5. */
+void orc_gamma(int mu, double *out /* [4][4][2] */)
+{
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cplx v = (mu < 4) ? GAM[mu][i][j] : GAM5[i][j];
+            out[(i * 4 + j) * 2 + 0] = creal(v);
+            out[(i * 4 + j) * 2 + 1] = cimag(v);
+        }
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice geometry                                                          */
+/* ------------------------------------------------------------------------ */
+static long volume4(const int L[4]) { return (long)L[0] * L[1] * L[2] * L[3]; }
+
+static void coords_of(const int L[4], long s, int c[4])
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        c[mu] = (int)(s % L[mu]);
+        s /= L[mu];
+    }
+}
+
+static long index_of(const int L[4], const int c[4])
+{
+    return c[0] + (long)L[0] * (c[1] + (long)L[1] * (c[2] + (long)L[2] * c[3]));
+}
+
+static int parity_of(const int c[4]) { return (c[0] + c[1] + c[2] + c[3]) & 1; }
+
+/* ------------------------------------------------------------------------ */
+/* The hopping term D_W at one site.                                        */
+/*   g5in != 0 : use (gamma5 psi) in place of psi (for M^dag = g5 M g5)      */
+/*   mask_par >= 0 : treat psi as zero on sites of that parity               */
+/* ------------------------------------------------------------------------ */
+static void spin_apply(const cplx m[4][4], const cplx in[4][3], cplx out[4][3])
+{
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) {
+            cplx s = 0;
+            for (int b = 0; b < 4; ++b) s += m[a][b] * in[b][i];
+            out[a][i] = s;
+        }
+}
+
+static void load_spinor(const cplx *psi, long s, int g5in, cplx v[4][3])
+{
+    cplx raw[4][3];
+    memcpy(raw, psi + s * 12, sizeof raw);
+    if (g5in)
+        spin_apply(GAM5, raw, v);
+    else
+        memcpy(v, raw, sizeof raw);
+}
+
+static void hop_site(const cplx *U, const cplx *psi, const int L[4],
+                     const cplx ph[4], long s, int g5in, int mask_par,
+                     cplx out[4][3])
+{
+    int c[4];
+    coords_of(L, s, c);
+    memset(out, 0, sizeof(cplx) * 12);
+    for (int mu = 0; mu < 4; ++mu) {
+        int cf[4], cb[4];
+        memcpy(cf, c, sizeof cf);
+        memcpy(cb, c, sizeof cb);
+        cf[mu] = (c[mu] + 1) % L[mu];
+        cb[mu] = (c[mu] - 1 + L[mu]) % L[mu];
+        long sf = index_of(L, cf), sb = index_of(L, cb);
+        cplx pf = (c[mu] == L[mu] - 1) ? ph[mu] : 1.0;
+        cplx pb = (c[mu] == 0) ? conj(ph[mu]) : 1.0;
+
+        cplx one_minus[4][4], one_plus[4][4];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                cplx d = (a == b) ? 1.0 : 0.0;
+                one_minus[a][b] = d - GAM[mu][a][b];
+                one_plus[a][b] = d + GAM[mu][a][b];
+            }
+
+        /* forward: f (1 - gamma_mu) U_mu(x) psi(x+mu) */
+        {
+            cplx v[4][3], w[4][3], r[4][3];
+            load_spinor(psi, sf, g5in, v);
+            if (mask_par >= 0 && parity_of(cf) == mask_par) memset(v, 0, sizeof v);
+            const cplx *u = U + (s * 4 + mu) * 9;
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    cplx acc = 0;
+                    for (int j = 0; j < 3; ++j) acc += u[i * 3 + j] * v[a][j];
+                    w[a][i] = acc;
+                }
+            spin_apply(one_minus, w, r);
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) out[a][i] += pf * r[a][i];
+        }
+        /* backward: b (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu) */
+        {
+            cplx v[4][3], w[4][3], r[4][3];
+            load_spinor(psi, sb, g5in, v);
+            if (mask_par >= 0 && parity_of(cb) == mask_par) memset(v, 0, sizeof v);
+            const cplx *u = U + (sb * 4 + mu) * 9;
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    cplx acc = 0;
+                    for (int j = 0; j < 3; ++j) acc += conj(u[j * 3 + i]) * v[a][j];
+                    w[a][i] = acc;
+                }
+            spin_apply(one_plus, w, r);
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) out[a][i] += pb * r[a][i];
+        }
+    }
+}
+
+/* M (or M^dag = g5 M g5) at one site: out = psi(x) - kappa D_W psi(x). */
+static void mop_site(const cplx *U, const cplx *psi, const int L[4],
+                     const cplx ph[4], double kappa, int dagger, long s,
+                     cplx out[4][3])
+{
+    cplx h[4][3], own[4][3], m[4][3];
+    hop_site(U, psi, L, ph, s, dagger, -1, h);
+    load_spinor(psi, s, dagger, own);
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) m[a][i] = own[a][i] - kappa * h[a][i];
+    if (dagger)
+        spin_apply(GAM5, m, out);
+    else
+        memcpy(out, m, sizeof m);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole-lattice operators (exported)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* out = D_W psi  (dagger: D_W^dag = g5 D_W g5) */
+void orc_dslash(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+                const cplx ph[4], int dagger)
+{
+    long V = volume4(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        cplx h[4][3];
+        hop_site(U, psi, L, ph, s, dagger, -1, h);
+        if (dagger)
+            spin_apply(GAM5, h, (cplx(*)[3])(out + s * 12));
+        else
+            memcpy(out + s * 12, h, sizeof h);
+    }
+}
+
+/* out = M psi = psi - kappa D_W psi  (dagger: M^dag = g5 M g5) */
+void orc_mop(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+             const cplx ph[4], double kappa, int dagger)
+{
+    long V = volume4(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s)
+        mop_site(U, psi, L, ph, kappa, dagger, s, (cplx(*)[3])(out + s * 12));
+}
+
+/* M (or M^dag) at a list of sites only: out[n][12]. */
+void orc_mop_sites(const cplx *U, const cplx *psi, const int L[4],
+                   const cplx ph[4], double kappa, int dagger,
+                   const int64_t *sites, long n, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k)
+        mop_site(U, psi, L, ph, kappa, dagger, (long)sites[k],
+                 (cplx(*)[3])(out + k * 12));
+}
+
+/* D_W (or D_W^dag) at a list of sites only: out[n][12]. */
+void orc_dslash_sites(const cplx *U, const cplx *psi, const int L[4],
+                      const cplx ph[4], int dagger, const int64_t *sites,
+                      long n, cplx *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        cplx h[4][3];
+        hop_site(U, psi, L, ph, (long)sites[k], dagger, -1, h);
+        if (dagger)
+            spin_apply(GAM5, h, (cplx(*)[3])(out + k * 12));
+        else
+            memcpy(out + k * 12, h, sizeof h);
+    }
+}
+
+/*
+ * Even-odd blocks of D_W (even = (x+y+z+t) even). With out_parity p this is
+ * D_{p,1-p}: the output lives on parity p and only the input on parity 1-p
+ * enters; the output on parity 1-p is zero. Whole-lattice canonical arrays.
+ */
+void orc_dslash_eo(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+                   const cplx ph[4], int out_parity, int dagger)
+{
+    long V = volume4(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        cplx h[4][3];
+        if (parity_of(c) != out_parity) {
+            memset(out + s * 12, 0, sizeof h);
+            continue;
+        }
+        hop_site(U, psi, L, ph, s, dagger, out_parity, h);
+        if (dagger)
+            spin_apply(GAM5, h, (cplx(*)[3])(out + s * 12));
+        else
+            memcpy(out + s * 12, h, sizeof h);
+    }
+}
+
+/*
+ * Schur complement on parity p:  Mhat = 1 - kappa^2 D_{p,1-p} D_{1-p,p}
+ * (dagger: g5 Mhat g5). Whole-lattice arrays; output is zero on parity 1-p.
+ */
+void orc_schur(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+               const cplx ph[4], double kappa, int parity, int dagger)
+{
+    long V = volume4(L);
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    cplx *tmp2 = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    orc_dslash_eo(U, psi, tmp, L, ph, 1 - parity, dagger);
+    orc_dslash_eo(U, tmp, tmp2, L, ph, parity, dagger);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        for (int k = 0; k < 12; ++k)
+            out[s * 12 + k] = (parity_of(c) == parity)
+                                  ? psi[s * 12 + k] - kappa * kappa * tmp2[s * 12 + k]
+                                  : 0.0;
+    }
+    free(tmp);
+    free(tmp2);
+}
+
+/* Mean plaquette: average over sites and the 6 planes of Re tr(U_mu nu)/3. */
+double orc_plaquette(const cplx *U, const int L[4])
+{
+    long V = volume4(L);
+    double sum = 0;
+#pragma omp parallel for schedule(static) reduction(+ : sum)
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                int cm[4], cn[4];
+                memcpy(cm, c, sizeof cm);
+                memcpy(cn, c, sizeof cn);
+                cm[mu] = (c[mu] + 1) % L[mu];
+                cn[nu] = (c[nu] + 1) % L[nu];
+                const cplx *a = U + (s * 4 + mu) * 9;                 /* U_mu(x)      */
+                const cplx *b = U + (index_of(L, cm) * 4 + nu) * 9;   /* U_nu(x+mu)   */
+                const cplx *e = U + (index_of(L, cn) * 4 + mu) * 9;   /* U_mu(x+nu)   */
+                const cplx *d = U + (s * 4 + nu) * 9;                 /* U_nu(x)      */
+                cplx ab[9], abe[9], tr = 0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        cplx acc = 0;
+                        for (int k = 0; k < 3; ++k) acc += a[i * 3 + k] * b[k * 3 + j];
+                        ab[i * 3 + j] = acc;
+                    }
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        cplx acc = 0;
+                        for (int k = 0; k < 3; ++k) acc += ab[i * 3 + k] * conj(e[j * 3 + k]);
+                        abe[i * 3 + j] = acc;
+                    }
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) tr += abe[i * 3 + k] * conj(d[i * 3 + k]);
+                sum += creal(tr) / 3.0;
+            }
+    }
+    return sum / (6.0 * V);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vector helpers (whole-lattice, n complex entries)                         */
+/* ------------------------------------------------------------------------ */
+static double vnorm2(const cplx *a, long n)
+{
+    double s = 0;
+#pragma omp parallel for schedule(static) reduction(+ : s)
+    for (long i = 0; i < n; ++i) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+static cplx vdot(const cplx *a, const cplx *b, long n) /* sum conj(a) b */
+{
+    double re = 0, im = 0;
+#pragma omp parallel for schedule(static) reduction(+ : re, im)
+    for (long i = 0; i < n; ++i) {
+        cplx v = conj(a[i]) * b[i];
+        re += creal(v);
+        im += cimag(v);
+    }
+    return re + I * im;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Solvers                                                                   */
+/* ------------------------------------------------------------------------ */
+/* A solve gives up after this many true-residual restarts (status 1). */
+#define ORC_MAX_RESTARTS 64
+
+typedef struct {
+    int32_t iterations;  /* Krylov iterations over all restarts */
+    int32_t restarts;    /* true-residual restarts */
+    double true_res;     /* ||b - M x|| / ||b|| recomputed at the end */
+} orc_stats;
+
+/*
+ * CG on the normal equations M^dag M x = M^dag b (Hestenes-Stiefel), x0 = x
+ * on entry. The CG loop stops when ||r_k|| <= eta ||M^dag b||; then the true
+ * residual rho = ||b - M x|| / ||b|| is recomputed, and CG restarts from x with
+ * eta <- eta * (tol / rho) / 2 until rho <= tol.
+ * Returns 0 when rho <= tol, 1 when maxiter (or the restart limit) was reached
+ * first, 2 when the residual is not finite.
+ */
+int orc_cgnr(const cplx *U, const cplx *b, cplx *x, const int L[4],
+             const cplx ph[4], double kappa, double tol, int maxiter,
+             orc_stats *st)
+{
+    long n = volume4(L) * 12;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *t = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    double bnorm = sqrt(vnorm2(b, n));
+    orc_mop(U, b, t, L, ph, kappa, 1);
+    double mbnorm = sqrt(vnorm2(t, n));
+    double eta = tol;
+    int it = 0, restarts = 0, status = 1;
+    double rho = 1.0;
+    for (;;) {
+        orc_mop(U, x, t, L, ph, kappa, 0);
+        for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+        orc_mop(U, t, r, L, ph, kappa, 1);
+        memcpy(p, r, sizeof(cplx) * n);
+        double rr = vnorm2(r, n);
+        while (rr > eta * eta * mbnorm * mbnorm && it < maxiter) {
+            orc_mop(U, p, t, L, ph, kappa, 0);
+            double pap = vnorm2(t, n);
+            if (!(pap > 0.0) || !isfinite(pap)) break;
+            double alpha = rr / pap;
+            orc_mop(U, t, q, L, ph, kappa, 1);
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            double rr_new = vnorm2(r, n);
+            double beta = rr_new / rr;
+            rr = rr_new;
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+            ++it;
+        }
+        orc_mop(U, x, t, L, ph, kappa, 0);
+        for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+        rho = sqrt(vnorm2(t, n)) / bnorm;
+        if (!isfinite(rho)) { status = 2; break; }
+        if (rho <= tol) { status = 0; break; }
+        if (it >= maxiter || restarts >= ORC_MAX_RESTARTS) { status = 1; break; }
+        eta = eta * (tol / rho) * 0.5;
+        ++restarts;
+    }
+    if (st) { st->iterations = it; st->restarts = restarts; st->true_res = rho; }
+    free(r); free(p); free(t); free(q);
+    return status;
+}
+
+/*
+ * BiCGStab on M x = b (van der Vorst 1992), x0 = x on entry, shadow residual
+ * rhat = r0. Stops on ||r|| / ||b|| <= tol, then recomputes the true residual;
+ * when that misses tol, or rho or omega vanish, it restarts from x with
+ * rhat = r. Returns 0 when the true residual is <= tol, 1 at maxiter (or the
+ * restart limit), 2 when the residual is not finite.
+ */
+int orc_bicgstab(const cplx *U, const cplx *b, cplx *x, const int L[4],
+                 const cplx ph[4], double kappa, double tol, int maxiter,
+                 orc_stats *st)
+{
+    long n = volume4(L) * 12;
+    cplx *r = malloc(sizeof(cplx) * n), *rh = malloc(sizeof(cplx) * n);
+    cplx *p = malloc(sizeof(cplx) * n), *v = malloc(sizeof(cplx) * n);
+    cplx *s = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    double bnorm = sqrt(vnorm2(b, n));
+    int it = 0, passes = 0, status = 1;
+    double res = 1.0;
+    for (;;) {
+        orc_mop(U, x, t, L, ph, kappa, 0);
+        for (long i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        res = sqrt(vnorm2(r, n)) / bnorm;
+        if (!isfinite(res)) { status = 2; break; }
+        if (res <= tol) { status = 0; break; }
+        if (it >= maxiter || passes > ORC_MAX_RESTARTS) { status = 1; break; }
+        ++passes;
+        memcpy(rh, r, sizeof(cplx) * n);
+        memset(p, 0, sizeof(cplx) * n);
+        memset(v, 0, sizeof(cplx) * n);
+        cplx rho_old = 1, alpha = 1, omega = 1;
+        while (it < maxiter) {
+            cplx rho = vdot(rh, r, n);
+            if (cabs(rho) == 0.0 || cabs(omega) == 0.0) break;
+            cplx beta = (rho / rho_old) * (alpha / omega);
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            orc_mop(U, p, v, L, ph, kappa, 0);
+            cplx rv = vdot(rh, v, n);
+            if (cabs(rv) == 0.0) break;
+            alpha = rho / rv;
+            for (long i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+            ++it;
+            if (sqrt(vnorm2(s, n)) <= tol * bnorm) {
+                for (long i = 0; i < n; ++i) x[i] += alpha * p[i];
+                break;
+            }
+            orc_mop(U, s, t, L, ph, kappa, 0);
+            double tt = vnorm2(t, n);
+            if (tt == 0.0) break;
+            omega = vdot(t, s, n) / tt;
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * p[i] + omega * s[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            rho_old = rho;
+            if (sqrt(vnorm2(r, n)) <= tol * bnorm) break;
+        }
+    }
+    if (st) { st->iterations = it; st->restarts = passes > 0 ? passes - 1 : 0; st->true_res = res; }
+    free(r); free(rh); free(p); free(v); free(s); free(t);
+    return status;
+}

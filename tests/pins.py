@@ -1,0 +1,313 @@
+"""Pins of the CPU oracle: facts fixed by the mathematics and the physics.
+
+Each ``pin_*`` takes an ``oracle.Oracle`` and raises AssertionError when the
+oracle disagrees with the fact. None of them re-types the oracle's stencil:
+they use closed forms (free-field plane waves), invariants (gamma5
+hermiticity, gauge covariance), a differently assembled dense operator, and
+library routines (LAPACK) or a different algorithm (Neumann series) for the
+solves. ``tests/test_oracle_mutants.py`` plants mistakes in copies of the
+oracle and checks that these pins catch each one.
+"""
+import itertools
+
+import numpy as np
+
+from paper_1112_5280_amd import synth
+from tests.dense_ref import dense_dslash, parity_index
+
+AP = np.array([1, 1, 1, -1], dtype=np.complex128)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) /
+                 max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def gammas(orc):
+    return [orc.gamma(mu) for mu in range(4)]
+
+
+# ---------------------------------------------------------------------------
+def pin_gamma_algebra(orc):
+    """Euclidean Clifford algebra, hermiticity, and the chiral gamma_5."""
+    g = gammas(orc)
+    g5 = orc.gamma(4)
+    for mu in range(4):
+        assert np.allclose(g[mu], g[mu].conj().T, atol=0), "gamma not Hermitian"
+        for nu in range(4):
+            ac = g[mu] @ g[nu] + g[nu] @ g[mu]
+            assert np.allclose(ac, 2.0 * (mu == nu) * np.eye(4), atol=1e-15)
+    assert np.allclose(g5, g[0] @ g[1] @ g[2] @ g[3], atol=1e-15)
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]), atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+def _momenta(dims, phases):
+    theta = np.angle(np.asarray(phases, dtype=np.complex128))
+    return [[(2 * np.pi * n + theta[mu]) / dims[mu] for n in range(dims[mu])]
+            for mu in range(4)]
+
+
+def _plane_wave(dims, p):
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly),
+                             np.arange(lx), indexing="ij")
+    ph = p[0] * x + p[1] * y + p[2] * z + p[3] * t
+    return np.exp(1j * ph).reshape(-1)
+
+
+def pin_free_field_plane_wave(orc, dims=(4, 6, 2, 8), kappa=0.13,
+                              phases=(np.exp(0.3j), np.exp(-1.1j), 1.0, -1.0)):
+    """Unit links: M e^{ipx} w = e^{ipx} A(p) w with
+    A(p) = (1 - 2 kappa sum cos p) + 2 i kappa sum sin(p_mu) gamma_mu, where the
+    momenta satisfy p_mu L_mu = theta_mu mod 2 pi (twisted boundaries).
+    Also checks that A's eigenvalues are 1 - 2k sum cos p +- 2ik sqrt(sum sin^2 p).
+    """
+    g = gammas(orc)
+    U = synth.gauge_unit(dims)
+    mom = _momenta(dims, phases)
+    rng = np.random.default_rng(5)
+    picks = [tuple(rng.integers(0, dims[mu]) for mu in range(4)) for _ in range(4)]
+    picks.append((0, 0, 0, 0))
+    for n in picks:
+        p = [mom[mu][n[mu]] for mu in range(4)]
+        A = (1 - 2 * kappa * sum(np.cos(p))) * np.eye(4) + \
+            2j * kappa * sum(np.sin(p[mu]) * g[mu] for mu in range(4))
+        wave = _plane_wave(dims, p)
+        w = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+        psi = wave[:, None, None] * w[None]
+        out = orc.mop(U, psi, dims, kappa, phases)
+        expect = wave[:, None, None] * (A @ w)[None]
+        assert rel(out, expect) < 1e-13, "plane wave not mapped by A(p)"
+        s = np.sqrt(sum(np.sin(x) ** 2 for x in p))
+        lam = np.linalg.eigvals(A)
+        c = 1 - 2 * kappa * sum(np.cos(p))
+        want = np.array([c - 2j * kappa * s] * 2 + [c + 2j * kappa * s] * 2)
+        assert _sorted_close(lam, want, 1e-13)
+
+
+def _dense_from_apply(apply, n):
+    cols = []
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1
+        cols.append(apply(e))
+    return np.stack(cols, axis=1)
+
+
+def _sorted_close(a, b, tol):
+    ka = np.lexsort((np.round(a.imag, 6), np.round(a.real, 6)))
+    kb = np.lexsort((np.round(b.imag, 6), np.round(b.real, 6)))
+    return np.max(np.abs(a[ka] - b[kb])) < tol
+
+
+def pin_free_field_spectrum(orc, dims=(2, 4, 2, 4), kappa=0.13):
+    """All 12V eigenvalues of M on unit links with antiperiodic time equal the
+    closed form 1 - 2k sum cos p +- 2ik sqrt(sum sin^2 p), each 6-fold, with
+    p_t = (2n+1) pi / L_t."""
+    V = int(np.prod(dims))
+    U = synth.gauge_unit(dims)
+    M = _dense_from_apply(
+        lambda e: orc.mop(U, e.reshape(V, 4, 3), dims, kappa, AP).reshape(-1),
+        12 * V)
+    ev = np.linalg.eigvals(M)
+    mom = _momenta(dims, AP)
+    want = []
+    for n in itertools.product(*[range(d) for d in dims]):
+        p = [mom[mu][n[mu]] for mu in range(4)]
+        c = 1 - 2 * kappa * sum(np.cos(p))
+        s = np.sqrt(sum(np.sin(x) ** 2 for x in p))
+        want += [c + 2j * kappa * s] * 6 + [c - 2j * kappa * s] * 6
+    assert _sorted_close(ev, np.array(want), 1e-10), "free-field spectrum"
+
+
+# ---------------------------------------------------------------------------
+def pin_dense_kron(orc, dims=(2, 4, 2, 4), seed=11, kappa=0.11):
+    """The oracle's D_W, M and their adjoints equal a dense operator assembled
+    independently from Kronecker blocks (extent-2 neighbours coincide)."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, seed)
+    phases = np.exp(1j * np.array([0.4, -0.9, 2.1, np.pi]))
+    D = dense_dslash(U, dims, gammas(orc), phases)
+    psi = synth.gaussian_spinor(dims, seed + 1)
+    v = psi.reshape(-1)
+    assert rel(orc.dslash(U, psi, dims, phases).reshape(-1), D @ v) < 1e-13
+    assert rel(orc.dslash(U, psi, dims, phases, dagger=True).reshape(-1),
+               D.conj().T @ v) < 1e-13
+    M = np.eye(12 * V) - kappa * D
+    assert rel(orc.mop(U, psi, dims, kappa, phases).reshape(-1), M @ v) < 1e-13
+    assert rel(orc.mop(U, psi, dims, kappa, phases, dagger=True).reshape(-1),
+               M.conj().T @ v) < 1e-13
+
+
+def pin_gamma5_hermiticity(orc, dims=(4, 4, 4, 4), kappa=0.12):
+    """<phi, M psi> = <g5 M g5 phi, psi> on a Haar field (Eq. 1 relies on it)."""
+    U = synth.gauge_haar(dims, 3)
+    phi = synth.gaussian_spinor(dims, 4)
+    psi = synth.gaussian_spinor(dims, 5)
+    lhs = np.vdot(phi, orc.mop(U, psi, dims, kappa))
+    rhs = np.vdot(orc.mop(U, phi, dims, kappa, dagger=True), psi)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs), "gamma5 hermiticity"
+    # and D_W itself
+    lhs = np.vdot(phi, orc.dslash(U, psi, dims))
+    rhs = np.vdot(orc.dslash(U, phi, dims, dagger=True), psi)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def gauge_transform(U, dims, omega):
+    """U^Omega_mu(x) = Omega(x) U_mu(x) Omega(x+mu)^dagger."""
+    V = int(np.prod(dims))
+    out = np.empty_like(U)
+    x, y, z, t = synth.site_coords(dims, np.arange(V))
+    c = [x, y, z, t]
+    for mu in range(4):
+        cf = list(c)
+        cf[mu] = (c[mu] + 1) % dims[mu]
+        sf = synth.site_index(dims, *cf)
+        out[:, mu] = omega @ U[:, mu] @ np.conj(np.swapaxes(omega[sf], 1, 2))
+    return out
+
+
+def pin_gauge_covariance(orc, dims=(4, 4, 2, 6), kappa=0.12):
+    """M[U^Omega](Omega psi) = Omega M[U] psi for random local SU(3) Omega."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, 7)
+    omega = synth.haar_su3(V, np.random.default_rng(8))
+    psi = synth.gaussian_spinor(dims, 9)
+    Ug = gauge_transform(U, dims, omega)
+    psig = np.einsum("sab,sib->sia", omega, psi)
+    lhs = orc.mop(Ug, psig, dims, kappa)
+    rhs = np.einsum("sab,sib->sia", omega, orc.mop(U, psi, dims, kappa))
+    assert rel(lhs, rhs) < 1e-13, "gauge covariance"
+
+
+# ---------------------------------------------------------------------------
+def pin_eo_split(orc, dims=(4, 2, 6, 4)):
+    """D_W = D_eo + D_oe; each block sees only the other parity's input."""
+    U = synth.gauge_haar(dims, 13)
+    psi = synth.gaussian_spinor(dims, 14)
+    from oracle import parity_mask
+    odd = parity_mask(dims)
+    for dag in (False, True):
+        full = orc.dslash(U, psi, dims, dagger=dag)
+        e = orc.dslash_eo(U, psi, dims, 0, dagger=dag)
+        o = orc.dslash_eo(U, psi, dims, 1, dagger=dag)
+        assert rel(e + o, full) < 1e-14
+        assert np.all(e[odd] == 0) and np.all(o[~odd] == 0)
+        junk = psi.copy()
+        junk[~odd] = 7.0  # even input must not enter D_{even,odd}
+        assert rel(orc.dslash_eo(U, junk, dims, 0, dagger=dag), e) < 1e-14
+
+
+def pin_schur_dense(orc, dims=(2, 4, 2, 4), kappa=0.13):
+    """Mhat = M_ee - M_eo M_oo^-1 M_oe by dense block elimination (and its
+    adjoint for the dagger), on both parities."""
+    U = synth.gauge_haar(dims, 15)
+    V = int(np.prod(dims))
+    D = dense_dslash(U, dims, gammas(orc), AP)
+    M = np.eye(12 * V) - kappa * D
+    ev, od = parity_index(dims)
+    psi = synth.gaussian_spinor(dims, 16)
+    for par, (a, b) in ((0, (ev, od)), (1, (od, ev))):
+        S = M[np.ix_(a, a)] - M[np.ix_(a, b)] @ np.linalg.solve(
+            M[np.ix_(b, b)], M[np.ix_(b, a)])
+        v = np.zeros(12 * V, dtype=np.complex128)
+        v[a] = psi.reshape(-1)[a]
+        for dag in (False, True):
+            out = orc.schur(U, v.reshape(V, 4, 3), dims, kappa, par,
+                            dagger=dag).reshape(-1)
+            want = (S.conj().T if dag else S) @ v[a]
+            assert rel(out[a], want) < 1e-13
+            assert np.all(out[b] == 0)
+
+
+def pin_sites(orc, dims=(4, 4, 2, 6), kappa=0.14):
+    """The site-sampled operators agree with the whole-lattice ones."""
+    U = synth.gauge_haar(dims, 17)
+    psi = synth.gaussian_spinor(dims, 18)
+    sites = np.random.default_rng(19).choice(synth.volume(dims), 37,
+                                             replace=False)
+    for dag in (False, True):
+        assert rel(orc.mop_sites(U, psi, dims, kappa, sites, dagger=dag),
+                   orc.mop(U, psi, dims, kappa, dagger=dag)[sites]) < 1e-15
+        assert rel(orc.dslash_sites(U, psi, dims, sites, dagger=dag),
+                   orc.dslash(U, psi, dims, dagger=dag)[sites]) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+def pin_solvers_lapack(orc, dims=(4, 4, 4, 4), kappa=0.12, maxiter=3000):
+    """CGNR and BiCGStab reach the LAPACK solution of the dense system."""
+    U = synth.gauge_haar(dims, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    V = int(np.prod(dims))
+    D = dense_dslash(U, dims, gammas(orc), AP)
+    M = np.eye(12 * V) - kappa * D
+    xs = np.linalg.solve(M, b.reshape(-1))
+    # ||D_W|| <= 8 for unitary links and unit phases, so for kappa < 1/8
+    # cond(M) <= (1 + 8 kappa) / (1 - 8 kappa)
+    cond = (1 + 8 * kappa) / (1 - 8 * kappa)
+    # CG on M^dag M contracts the error by (c - 1)/(c + 1) per step with
+    # c = cond(M), so ln(2/tol) c / 2 steps suffice; on so well-conditioned a
+    # system the recursive residual tracks the true one to rounding, so a
+    # correct method needs at most a couple of true-residual restarts.
+    it_bound = cond * np.log(2 / 1e-10) / 2
+    for solver in (orc.cgnr, orc.bicgstab):
+        x, st = solver(U, b, dims, kappa, tol=1e-10, maxiter=maxiter)
+        assert st["status"] == 0, st
+        res = np.linalg.norm(b.reshape(-1) - M @ x.reshape(-1)) / np.linalg.norm(b)
+        assert res <= 1e-10, res
+        assert rel(x.reshape(-1), xs) <= cond * 1e-10
+        assert st["restarts"] <= 2 and st["iterations"] <= it_bound, st
+
+
+def pin_neumann(orc, dims=(4, 4, 2, 4), kappa=0.12):
+    """For kappa < 1/8, x = sum_k (kappa D_W)^k b (a different algorithm)."""
+    U = synth.gauge_haar(dims, 21)
+    b = synth.gaussian_spinor(dims, 22)
+    term = b.copy()
+    x = b.copy()
+    for _ in range(2000):
+        term = kappa * orc.dslash(U, term, dims)
+        x = x + term
+        if np.linalg.norm(term) < 1e-15 * np.linalg.norm(b):
+            break
+    xc, st = orc.cgnr(U, b, dims, kappa, tol=1e-12, maxiter=3000)
+    assert st["status"] == 0
+    assert rel(xc, x) < 1e-10
+
+
+def pin_free_field_solve(orc, dims=(4, 2, 4, 8), kappa=0.12):
+    """Unit links: the source e^{ipx} w, w an eigenvector of A(p), has the
+    solution e^{ipx} w / lambda."""
+    g = gammas(orc)
+    U = synth.gauge_unit(dims)
+    mom = _momenta(dims, AP)
+    p = [mom[0][1], mom[1][1], mom[2][3], mom[3][2]]
+    A = (1 - 2 * kappa * sum(np.cos(p))) * np.eye(4) + \
+        2j * kappa * sum(np.sin(p[mu]) * g[mu] for mu in range(4))
+    lam, vec = np.linalg.eig(A)
+    w = np.outer(vec[:, 0], np.array([0.3, -1.0j, 0.7]))
+    b = _plane_wave(dims, p)[:, None, None] * w[None]
+    for solver in (orc.cgnr, orc.bicgstab):
+        x, st = solver(U, b, dims, kappa, tol=1e-12, maxiter=3000)
+        assert st["status"] == 0
+        assert rel(x, b / lam[0]) < 1e-10
+
+
+def pin_plaquette(orc, dims=(4, 4, 2, 4)):
+    """Unit links give plaquette 1; the plaquette is gauge invariant."""
+    assert abs(orc.plaquette(synth.gauge_unit(dims), dims) - 1.0) < 1e-15
+    V = int(np.prod(dims))
+    U = synth.gauge_smooth(dims, 0.3, 23)
+    omega = synth.haar_su3(V, np.random.default_rng(24))
+    p0 = orc.plaquette(U, dims)
+    p1 = orc.plaquette(gauge_transform(U, dims, omega), dims)
+    assert abs(p0 - p1) < 1e-13
+
+
+ALL_PINS = [
+    pin_gamma_algebra, pin_free_field_plane_wave, pin_free_field_spectrum,
+    pin_dense_kron, pin_gamma5_hermiticity, pin_gauge_covariance,
+    pin_eo_split, pin_schur_dense, pin_sites, pin_solvers_lapack,
+    pin_neumann, pin_free_field_solve, pin_plaquette,
+]
