@@ -1,0 +1,175 @@
+/*
+ * wilson.h -- C ABI of libwilson.so: the Wilson-Dirac fermion matrix and its
+ * Krylov solves on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper, Sec. 3 and Sec. 4): the fermion matrix of Wilson-type
+ * fermions, M = 1 - kappa D_W, whose non-diagonal part D_W ("dslash") is the
+ * 8-neighbour SU(3) x spin hopping stencil
+ *
+ *   D_W psi(x) = sum_mu [ f_mu(x) (1 - gamma_mu) U_mu(x)        psi(x+mu)
+ *                       + b_mu(x) (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *
+ * even-odd preconditioning of M, and the inversion x = M^-1 b (the point-source
+ * propagators of Eq. 1 are 12 such solves). The paper does not print these
+ * formulas; this library uses the standard definitions:
+ *   - Euclidean chiral gamma basis, gamma_5 = gamma_x gamma_y gamma_z gamma_t
+ *     = diag(1, 1, -1, -1); M^dag = gamma_5 M gamma_5;
+ *   - boundary phases: a forward hop that wraps (x_mu = L_mu - 1) is multiplied
+ *     by phase_mu, a backward hop that wraps (x_mu = 0) by conj(phase_mu); the
+ *     usual choice is (1, 1, 1, -1): periodic in space, antiperiodic in time.
+ *   - even sites: (x + y + z + t) even. Schur complement on parity p:
+ *     Mhat_p = 1 - kappa^2 D_{p,1-p} D_{1-p,p}.
+ *
+ * Lattice: dims = {Lx, Ly, Lz, Lt}; every extent must be even and >= 2 (the
+ * even-odd layout needs it). Canonical site index s = x + Lx*(y + Ly*(z + Lz*t)).
+ *
+ * Buffers and ownership. Every data pointer is DEVICE memory owned by the
+ * caller; the library borrows it for stream-ordered work and keeps no
+ * reference after the call's work completes. Kernels run on the HIP stream
+ * passed as `stream` (a hipStream_t; NULL = the null stream); the dslash calls
+ * return as soon as the work is enqueued, the solvers return after it is done.
+ * Nothing may alias: in != out, b != x, and no buffer may overlap `work`.
+ *
+ * Packed layouts ("WL layout"), produced by wl_pack_* and consumed by every
+ * operator and solver. With Vh = V/2 and S = Vh rounded up to a multiple of 64:
+ *   spinor (full field): [parity][chunk][S], parity 0 = even block first;
+ *     a half field (one parity) is one [chunk][S] block, wl_spinor_bytes(.., 1).
+ *     FP64: 12 chunks of double2 (one complex each, index spin*3 + colour);
+ *     FP32: 6 chunks of float4 (two consecutive complex components each).
+ *   gauge: [parity][mu][chunk][S]; link U_mu(x) stored at the parity and
+ *     checkerboard index of x. 18-real: the 9 complex entries, row-major;
+ *     12-real (WL_LINK12): rows 0 and 1 only, row 2 = conj(row0 x row1) is
+ *     rebuilt in the kernel (exact for det U = 1). FP64: one complex per
+ *     double2 chunk; FP32: float2 per complex (18-real), float4 per complex
+ *     pair (12-real).
+ *   Checkerboard index of site s (with parity (x+y+z+t) & 1) is s / 2.
+ *   Padding entries (checkerboard index >= Vh) are never read or written by
+ *   the operators.
+ *
+ * Errors: 0 = WL_OK; positive = a solve finished without reaching tol (x holds
+ * the best iterate seen, stats->true_res is set); negative = nothing was done.
+ * No exceptions cross the ABI. wl_last_error() returns a thread-local message
+ * for the last non-zero return on the calling thread.
+ */
+#ifndef WILSON_H
+#define WILSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- flags --------------------------------------------------------------- */
+#define WL_F64        0x0u   /* storage and arithmetic precision: FP64        */
+#define WL_F32        0x1u   /* FP32                                          */
+#define WL_PREC_MASK  0x3u
+#define WL_LINK18     0x0u   /* links stored as 18 reals                      */
+#define WL_LINK12     0x4u   /* links stored as 12 reals (rows 0, 1)          */
+#define WL_DAG        0x8u   /* apply the adjoint (M^dag, D_W^dag, Mhat^dag)  */
+#define WL_HOP        0x10u  /* return the hopping term only (no 1 - kappa.)  */
+#define WL_EO         0x20u  /* solvers: even-odd (Schur) preconditioning     */
+#define WL_MIXED      0x40u  /* solvers: FP32 inner solve, FP64 outer loop    */
+#define WL_X0         0x80u  /* solvers: x holds the initial guess            */
+
+/* ---- status codes -------------------------------------------------------- */
+#define WL_OK          0
+#define WL_NOCONV      1     /* maxiter reached                               */
+#define WL_BREAKDOWN   2     /* a Krylov scalar vanished or became non-finite */
+#define WL_STAGNATED   3     /* no new best residual for a long stretch       */
+#define WL_EINVAL     (-1)   /* bad dims, phases, flags, null or aliasing     */
+#define WL_EWORKSPACE (-2)   /* work_bytes < wl_workspace_bytes(...)          */
+#define WL_EHIP       (-3)   /* a HIP runtime call failed                     */
+
+typedef struct {
+    int32_t status;           /* same value the solver returned               */
+    int32_t iterations;       /* Krylov iterations over all restarts          */
+    int32_t restarts;         /* true-residual restarts / outer corrections   */
+    int32_t op_applies;       /* operator applications (M, Mhat or adjoint)   */
+    double true_res;          /* ||b - M x|| / ||b||, FP64, full lattice      */
+    double seconds;           /* wall time of the solve                       */
+    double flops;             /* model flops (1320/site per D_W)              */
+    double bytes;             /* algorithmic bytes moved by all kernels       */
+} wl_solve_stats;
+
+/* Library version string and the thread-local message of the last error. */
+const char *wl_version(void);
+const char *wl_last_error(void);
+
+/* Bytes of a packed spinor with `nparity` (1 = half field, 2 = full field)
+ * parity blocks, or of a packed gauge field, for the precision and link format
+ * in `flags`. Returns 0 for invalid dims. */
+size_t wl_spinor_bytes(const int32_t dims[4], uint32_t flags, int32_t nparity);
+size_t wl_gauge_bytes(const int32_t dims[4], uint32_t flags);
+
+/* Canonical -> packed gauge field. `canon` is complex128 U[V][4][3][3] on the
+ * device (U[s][mu] on the bond s -> s+mu); `packed` receives
+ * wl_gauge_bytes(dims, flags) bytes in the precision and link format of
+ * `flags`. Asynchronous on `stream`. */
+int wl_pack_gauge(const void *canon, void *packed, const int32_t dims[4],
+                  uint32_t flags, void *stream);
+
+/* Canonical complex128 psi[V][4][3] <-> packed full spinor in the precision of
+ * `flags`. Asynchronous on `stream`. */
+int wl_pack_spinor(const void *canon, void *packed, const int32_t dims[4],
+                   uint32_t flags, void *stream);
+int wl_unpack_spinor(const void *packed, void *canon, const int32_t dims[4],
+                     uint32_t flags, void *stream);
+
+/* Full-lattice operator (paper Sec. 3, "dslash"; the fermion matrix M).
+ *   default:          out = M psi       = psi - kappa D_W psi
+ *   WL_HOP:           out = D_W psi
+ *   WL_DAG:           adjoint of the above (gamma_5-conjugate)
+ * `gauge` packed per flags; `in`, `out` packed full spinors in the same
+ * precision. phases = {re0, im0, re1, im1, re2, im2, re3, im3}, |phase| = 1.
+ * Asynchronous on `stream`; returns WL_EINVAL without enqueuing anything on a
+ * bad argument. */
+int wilson_dslash(const void *gauge, const void *in, void *out,
+                  const int32_t dims[4], double kappa, const double phases[8],
+                  uint32_t flags, void *stream);
+
+/* Even-odd operator (paper Sec. 3: the even-odd preconditioned dslash).
+ *   WL_HOP:   out (half field, parity out_parity)
+ *               = D_{p,1-p} in   (in: half field of parity 1 - out_parity)
+ *   default:  out = Mhat_p in = in - kappa^2 D_{p,1-p} D_{1-p,p} in,
+ *             in and out both half fields of parity p = out_parity; the
+ *             intermediate half field is taken from the stream-ordered
+ *             allocator of `stream`.
+ *   WL_DAG:   adjoint of the above.
+ * Asynchronous on `stream`. */
+int wilson_dslash_eo(const void *gauge, const void *in, void *out,
+                     const int32_t dims[4], double kappa,
+                     const double phases[8], int32_t out_parity,
+                     uint32_t flags, void *stream);
+
+/* Scratch bytes the solvers need for these dims and flags (nrhs = 1). */
+size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
+
+/* Solve M x = b (paper Sec. 4: the inversion S ~ M^-1 b) to
+ * ||b - M x|| / ||b|| <= tol, the residual recomputed in FP64 on the full
+ * lattice with the FP64 operator.
+ *   solve_cg:       conjugate gradient on M^dag M x = M^dag b (CGNR);
+ *   solve_bicgstab: BiCGStab on M.
+ * With WL_EO both run on the Schur system Mhat_e x_e = b_e + kappa D_eo b_o and
+ * reconstruct x_o = b_o + kappa D_oe x_e. With WL_MIXED the Krylov iterations
+ * run in FP32 (FP32 links and spinors) inside an FP64 defect-correction loop.
+ * `gauge` is the packed FP64 gauge field (link format per flags); `b` and `x`
+ * are packed FP64 full spinors; x is the initial guess with WL_X0, otherwise
+ * it is overwritten from zero. `work` is device scratch of at least
+ * wl_workspace_bytes(dims, flags, 1) bytes. `stats` (host memory) may be NULL.
+ * Blocks until the solve is complete. */
+int solve_cg(const void *gauge, const void *b, void *x, const int32_t dims[4],
+             double kappa, const double phases[8], double tol, int32_t maxiter,
+             uint32_t flags, void *work, size_t work_bytes,
+             wl_solve_stats *stats, void *stream);
+int solve_bicgstab(const void *gauge, const void *b, void *x,
+                   const int32_t dims[4], double kappa, const double phases[8],
+                   double tol, int32_t maxiter, uint32_t flags, void *work,
+                   size_t work_bytes, wl_solve_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_H */

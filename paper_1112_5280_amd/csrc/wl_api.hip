@@ -1,0 +1,320 @@
+// wl_api.hip -- the extern "C" boundary of libwilson.so (declared in
+// include/wilson.h): argument validation, error reporting and dispatch to the
+// launchers and solver drivers. No exception crosses this boundary.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "wl_internal.h"
+
+namespace wl {
+
+
+bool make_geom(const int32_t dims[4], Geom *g, std::string *why) {
+    if (!dims) {
+        *why = "dims is NULL";
+        return false;
+    }
+    long v = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (dims[mu] < 2 || (dims[mu] & 1)) {
+            *why = "every lattice extent must be even and >= 2 (got dims[" + std::to_string(mu) +
+                   "] = " + std::to_string(dims[mu]) + ")";
+            return false;
+        }
+        v *= dims[mu];
+        g->L[mu] = dims[mu];
+    }
+    // 36 link chunks per parity block must stay addressable with 32-bit offsets
+    if (v / 2 * 36 >= (1L << 31) - 64 * 36) {
+        *why = "lattice too large for this build (V = " + std::to_string(v) + ")";
+        return false;
+    }
+    g->Lxh = dims[0] / 2;
+    g->Vh = int(v / 2);
+    g->S = (g->Vh + 63) / 64 * 64;
+    g->bpp = (g->Vh + kBlock - 1) / kBlock;
+    return true;
+}
+
+size_t spinor_block_bytes(const Geom &g, int prec) {
+    return size_t(g.S) * 12 * (prec == WL_F64 ? 16 : 8);
+}
+
+size_t gauge_bytes(const Geom &g, int prec, bool link12) {
+    return size_t(2) * 4 * (link12 ? 6 : 9) * (prec == WL_F64 ? 16 : 8) * size_t(g.S);
+}
+
+}  // namespace wl
+
+using namespace wl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+constexpr uint32_t kKnownFlags = WL_PREC_MASK | WL_LINK12 | WL_DAG | WL_HOP | WL_EO | WL_MIXED |
+                                 WL_X0;
+
+bool get_prec(uint32_t flags, int *prec, std::string *why) {
+    const uint32_t p = flags & WL_PREC_MASK;
+    if (p != WL_F64 && p != WL_F32) {
+        *why = "unsupported precision flag";
+        return false;
+    }
+    *prec = int(p);
+    return true;
+}
+
+bool get_phases(const double *phases, Phases *ph, std::string *why) {
+    if (!phases) {
+        *why = "phases is NULL";
+        return false;
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        const double re = phases[2 * mu], im = phases[2 * mu + 1];
+        if (!std::isfinite(re) || !std::isfinite(im) || std::fabs(std::hypot(re, im) - 1.0) > 1e-12) {
+            *why = "boundary phase " + std::to_string(mu) + " is not of unit modulus";
+            return false;
+        }
+        ph->re[mu] = re;
+        ph->im[mu] = im;
+    }
+    return true;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(WL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wl_version(void) { return "wilson-mi355x 0.1 (gfx950)"; }
+
+const char *wl_last_error(void) { return g_last_error.c_str(); }
+
+size_t wl_spinor_bytes(const int32_t dims[4], uint32_t flags, int32_t nparity) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why) || nparity < 1 || nparity > 2)
+        return 0;
+    return spinor_block_bytes(g, prec) * size_t(nparity);
+}
+
+size_t wl_gauge_bytes(const int32_t dims[4], uint32_t flags) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why)) return 0;
+    return gauge_bytes(g, prec, flags & WL_LINK12);
+}
+
+int wl_pack_gauge(const void *canon, void *packed, const int32_t dims[4], uint32_t flags,
+                  void *stream) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why)) return fail(WL_EINVAL, why);
+    if (!canon || !packed) return fail(WL_EINVAL, "NULL buffer");
+    if (canon == packed) return fail(WL_EINVAL, "canon and packed alias");
+    const hipError_t e = launch_pack_gauge(g, prec, flags & WL_LINK12, canon, packed,
+                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_pack_gauge");
+}
+
+int wl_pack_spinor(const void *canon, void *packed, const int32_t dims[4], uint32_t flags,
+                   void *stream) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why)) return fail(WL_EINVAL, why);
+    if (!canon || !packed) return fail(WL_EINVAL, "NULL buffer");
+    if (canon == packed) return fail(WL_EINVAL, "canon and packed alias");
+    const hipError_t e = launch_pack_spinor(g, prec, canon, packed, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_pack_spinor");
+}
+
+int wl_unpack_spinor(const void *packed, void *canon, const int32_t dims[4], uint32_t flags,
+                     void *stream) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why)) return fail(WL_EINVAL, why);
+    if (!canon || !packed) return fail(WL_EINVAL, "NULL buffer");
+    if (canon == packed) return fail(WL_EINVAL, "canon and packed alias");
+    const hipError_t e = launch_unpack_spinor(g, prec, packed, canon,
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_unpack_spinor");
+}
+
+int wilson_dslash(const void *gauge, const void *in, void *out, const int32_t dims[4],
+                  double kappa, const double phases[8], uint32_t flags, void *stream) {
+    Geom g;
+    Phases ph;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why) ||
+        !get_phases(phases, &ph, &why))
+        return fail(WL_EINVAL, why);
+    if (!gauge || !in || !out) return fail(WL_EINVAL, "NULL buffer");
+    if (in == out) return fail(WL_EINVAL, "in and out alias");
+    if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    const size_t blk = spinor_block_bytes(g, prec);
+    HopCall c{};
+    c.gauge = gauge;
+    c.in[0] = in;
+    c.in[1] = static_cast<const char *>(in) + blk;
+    c.out[0] = out;
+    c.out[1] = static_cast<char *>(out) + blk;
+    if (!(flags & WL_HOP)) {
+        c.xs[0] = c.in[0];
+        c.xs[1] = c.in[1];
+        c.c = -kappa;
+    } else {
+        c.c = 1.0;
+    }
+    c.first_par = 0;
+    c.npar = 2;
+    c.dag = flags & WL_DAG;
+    const hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c,
+                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash");
+}
+
+int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t dims[4],
+                     double kappa, const double phases[8], int32_t out_parity, uint32_t flags,
+                     void *stream) {
+    Geom g;
+    Phases ph;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why) ||
+        !get_phases(phases, &ph, &why))
+        return fail(WL_EINVAL, why);
+    if (!gauge || !in || !out) return fail(WL_EINVAL, "NULL buffer");
+    if (in == out) return fail(WL_EINVAL, "in and out alias");
+    if (out_parity != 0 && out_parity != 1) return fail(WL_EINVAL, "out_parity must be 0 or 1");
+    if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int p = out_parity, q = 1 - out_parity;
+    const bool dag = flags & WL_DAG;
+    if (flags & WL_HOP) {
+        HopCall c{};
+        c.gauge = gauge;
+        c.in[q] = in;
+        c.out[p] = out;
+        c.first_par = p;
+        c.npar = 1;
+        c.c = 1.0;
+        c.dag = dag;
+        const hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c, s);
+        return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_eo");
+    }
+    // Schur complement: tmp_q = D_{q,p} in; out = in - kappa^2 D_{p,q} tmp_q
+    void *tmp = nullptr;
+    hipError_t e = hipMallocAsync(&tmp, spinor_block_bytes(g, prec), s);
+    if (e != hipSuccess) return hip_fail(e, "wilson_dslash_eo: scratch allocation");
+    HopCall c1{};
+    c1.gauge = gauge;
+    c1.in[p] = in;
+    c1.out[q] = tmp;
+    c1.first_par = q;
+    c1.npar = 1;
+    c1.c = 1.0;
+    c1.dag = dag;
+    e = launch_hop(g, prec, flags & WL_LINK12, ph, c1, s);
+    if (e == hipSuccess) {
+        HopCall c2{};
+        c2.gauge = gauge;
+        c2.in[q] = tmp;
+        c2.xs[p] = in;
+        c2.out[p] = out;
+        c2.first_par = p;
+        c2.npar = 1;
+        c2.c = -kappa * kappa;
+        c2.dag = dag;
+        e = launch_hop(g, prec, flags & WL_LINK12, ph, c2, s);
+    }
+    const hipError_t ef = hipFreeAsync(tmp, s);
+    if (e != hipSuccess) return hip_fail(e, "wilson_dslash_eo");
+    if (ef != hipSuccess) return hip_fail(ef, "wilson_dslash_eo: scratch release");
+    return WL_OK;
+}
+
+size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why) || nrhs < 1) return 0;
+    return workspace_bytes(g, flags) * size_t(nrhs);
+}
+
+static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
+                        const int32_t dims[4], double kappa, const double phases[8], double tol,
+                        int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                        wl_solve_stats *stats, void *stream) {
+    SolveIn in{};
+    std::string why;
+    if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
+        return fail(WL_EINVAL, why);
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    if ((flags & WL_PREC_MASK) != WL_F64)
+        return fail(WL_EINVAL, "solver buffers are FP64 (use WL_MIXED for an FP32 inner solve)");
+    if (flags & (WL_DAG | WL_HOP)) return fail(WL_EINVAL, "WL_DAG / WL_HOP do not apply to solves");
+    if (!gauge || !b || !x || !work) return fail(WL_EINVAL, "NULL buffer");
+    if (b == x) return fail(WL_EINVAL, "b and x alias");
+    if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WL_EINVAL, "tol must be positive");
+    if (maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
+    const size_t need = workspace_bytes(in.g, flags);
+    if (work_bytes < need)
+        return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                       " bytes, got " + std::to_string(work_bytes));
+    in.gauge = gauge;
+    in.b = b;
+    in.x = x;
+    in.kappa = kappa;
+    in.tol = tol;
+    in.maxiter = maxiter;
+    in.flags = flags;
+    in.work = work;
+    in.s = static_cast<hipStream_t>(stream);
+    const int st = run_solver(bicg, in, stats, &why);
+    if (st != WL_OK) {
+        if (why.empty()) {
+            static const char *names[] = {"ok", "not converged within maxiter",
+                                          "breakdown (a Krylov scalar vanished or is not finite)",
+                                          "stagnated"};
+            why = st > 0 && st < 4 ? names[st] : "error";
+        }
+        g_last_error = why;
+    }
+    return st;
+}
+
+int solve_cg(const void *gauge, const void *b, void *x, const int32_t dims[4], double kappa,
+             const double phases[8], double tol, int32_t maxiter, uint32_t flags, void *work,
+             size_t work_bytes, wl_solve_stats *stats, void *stream) {
+    return solve_common(false, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
+                        work_bytes, stats, stream);
+}
+
+int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims[4],
+                   double kappa, const double phases[8], double tol, int32_t maxiter,
+                   uint32_t flags, void *work, size_t work_bytes, wl_solve_stats *stats,
+                   void *stream) {
+    return solve_common(true, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
+                        work_bytes, stats, stream);
+}
+
+}  // extern "C"

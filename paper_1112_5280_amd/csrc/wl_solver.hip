@@ -1,0 +1,479 @@
+// wl_solver.hip -- Krylov solvers for M x = b (paper Sec. 4: the inversion of
+// the fermion matrix for point-source propagators; Sec. 3: even-odd
+// preconditioning).
+//
+//   CGNR      Hestenes-Stiefel CG on M^dag M x = M^dag b.
+//   BiCGStab  van der Vorst's BiCGStab on M.
+//   WL_EO     both run on the Schur system Mhat_e x_e = b_e + kappa D_eo b_o,
+//             Mhat_e = 1 - kappa^2 D_eo D_oe, then x_o = b_o + kappa D_oe x_e.
+//   WL_MIXED  FP64 defect correction: r = b - M x in FP64, an FP32 Krylov solve
+//             of M e = r to a relative 1e-5, x += e in FP64, until the FP64
+//             true residual meets tol.
+//
+// Every solve finishes with the FP64 true residual ||b - M x|| / ||b|| on the
+// full lattice; when it misses tol the Krylov loop restarts from x with a
+// tighter inner target. The Krylov loops keep all scalars on the device; the
+// host enqueues a chunk of iterations and then reads one small status block.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "wl_internal.h"
+
+namespace wl {
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+constexpr int kVec64 = 8;   // FP64 full spinors
+constexpr int kVec32 = 10;  // FP32 full spinors (mixed precision)
+constexpr size_t kAlign = 256;
+
+static size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Workspace {
+    Scalars *sc;
+    unsigned *counter;
+    double *partials;
+    char *v64[kVec64];
+    void *gauge32;
+    char *v32[kVec32];
+};
+
+static size_t header_bytes(const Geom &g) {
+    return align_up(4096 + sizeof(double) * kMaxSums * 2 * size_t(g.bpp));
+}
+
+size_t workspace_bytes(const Geom &g, uint32_t flags) {
+    size_t n = header_bytes(g) + kVec64 * align_up(2 * spinor_block_bytes(g, WL_F64));
+    if (flags & WL_MIXED)
+        n += align_up(gauge_bytes(g, WL_F32, flags & WL_LINK12)) +
+             kVec32 * align_up(2 * spinor_block_bytes(g, WL_F32));
+    return n;
+}
+
+static Workspace carve(const Geom &g, uint32_t flags, void *work) {
+    Workspace ws{};
+    char *p = static_cast<char *>(work);
+    ws.sc = reinterpret_cast<Scalars *>(p);
+    ws.counter = reinterpret_cast<unsigned *>(p + 1024);
+    ws.partials = reinterpret_cast<double *>(p + 4096);
+    p += header_bytes(g);
+    const size_t f64 = align_up(2 * spinor_block_bytes(g, WL_F64));
+    for (int k = 0; k < kVec64; ++k, p += f64) ws.v64[k] = p;
+    if (flags & WL_MIXED) {
+        ws.gauge32 = p;
+        p += align_up(gauge_bytes(g, WL_F32, flags & WL_LINK12));
+        const size_t f32 = align_up(2 * spinor_block_bytes(g, WL_F32));
+        for (int k = 0; k < kVec32; ++k, p += f32) ws.v32[k] = p;
+    }
+    return ws;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side status readback
+// ---------------------------------------------------------------------------
+struct Fail {
+    hipError_t err;
+};
+
+static void check(hipError_t e) {
+    if (e != hipSuccess) throw Fail{e};
+}
+
+static Scalars *host_scalars() {
+    thread_local Scalars *h = nullptr;
+    if (!h) check(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Scalars), hipHostMallocDefault));
+    return h;
+}
+
+static Scalars read_scalars(const Scalars *dev, hipStream_t s) {
+    Scalars *h = host_scalars();
+    check(hipMemcpyAsync(h, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    return *h;
+}
+
+// ---------------------------------------------------------------------------
+// The operator of a Krylov solve, in one storage precision
+// ---------------------------------------------------------------------------
+struct Space {
+    const Geom *g;
+    int prec;
+    bool link12;
+    Phases ph;
+    const void *gauge;
+    double kappa;
+    bool eo;
+    hipStream_t s;
+    Scalars *sc;
+    unsigned *counter;
+    double *partials;
+    void *tmp;               // one parity block for the eo intermediate
+    // model cost bookkeeping
+    double applies = 0;      // applications of A or A^dag
+
+    int npar() const { return eo ? 1 : 2; }
+    size_t blk() const { return spinor_block_bytes(*g, prec); }
+    void *par(void *full, int q) const { return static_cast<char *>(full) + q * blk(); }
+    const void *par(const void *full, int q) const {
+        return static_cast<const char *>(full) + q * blk();
+    }
+
+    Reduce red(int epi) const { return Reduce{partials, counter, sc->sums, epi, sc}; }
+
+    // out = A in, A = M (full) or Mhat_e (eo), or the adjoint; optional fused
+    // reduction (norm of out / <aux, out> / <out, in> and ||out||^2).
+    void apply(const void *in, void *out, bool dag, int epi, const void *aux, const int *skip) {
+        const Reduce r = red(epi);
+        const Reduce *rp = epi == kEpiNone ? nullptr : &r;
+        if (!eo) {
+            HopCall c{};
+            c.gauge = gauge;
+            c.in[0] = in; c.in[1] = par(in, 1);
+            c.xs[0] = in; c.xs[1] = par(in, 1);
+            c.aux[0] = aux; c.aux[1] = aux ? par(aux, 1) : nullptr;
+            c.out[0] = out; c.out[1] = par(out, 1);
+            c.first_par = 0; c.npar = 2; c.c = -kappa; c.dag = dag; c.skip = skip; c.red = rp;
+            check(launch_hop(*g, prec, link12, ph, c, s));
+        } else {
+            HopCall c1{};
+            c1.gauge = gauge;
+            c1.in[0] = in;
+            c1.out[1] = tmp;
+            c1.first_par = 1; c1.npar = 1; c1.c = 1.0; c1.dag = dag; c1.skip = skip;
+            check(launch_hop(*g, prec, link12, ph, c1, s));
+            HopCall c2{};
+            c2.gauge = gauge;
+            c2.in[1] = tmp;
+            c2.xs[0] = in;
+            c2.aux[0] = aux;
+            c2.out[0] = out;
+            c2.first_par = 0; c2.npar = 1; c2.c = -kappa * kappa; c2.dag = dag; c2.skip = skip;
+            c2.red = rp;
+            check(launch_hop(*g, prec, link12, ph, c2, s));
+        }
+        applies += 1;
+    }
+
+    void blas(int op, void *v0, void *v1 = nullptr, void *v2 = nullptr, void *v3 = nullptr,
+              void *v4 = nullptr, void *v5 = nullptr, int epi = kEpiNone, bool use_skip = true,
+              double a = 0.0) {
+        const Reduce r = red(epi);
+        BlasCall c{};
+        c.op = op;
+        c.npar = npar();
+        c.v[0] = v0; c.v[1] = v1; c.v[2] = v2; c.v[3] = v3; c.v[4] = v4; c.v[5] = v5;
+        c.a = a;
+        c.sc = sc;
+        c.skip = use_skip ? &sc->done : nullptr;
+        c.red = (op == kOpNorm2 || op == kOpXmy || op == kOpCgXR || op == kOpBiXR ||
+                 op == kOpCopyNorm2 || op == kOpCopy2Norm2) ? &r : nullptr;
+        check(launch_blas(*g, prec, c, s));
+    }
+
+    // sum0 of the last reduction, read back to the host
+    double norm2(const void *v) {
+        blas(kOpNorm2, const_cast<void *>(v), nullptr, nullptr, nullptr, nullptr, nullptr,
+             kEpiNone, false);
+        return read_scalars(sc, s).sums[0];
+    }
+};
+
+// Iterations per host check: small enough to stop soon after convergence,
+// large enough to hide the readback.
+static int chunk_for(const Geom &g) { return g.Vh >= (1 << 18) ? 4 : 16; }
+
+// ---------------------------------------------------------------------------
+// CGNR core: iterate on A^dag A x = A^dag rhs until ||r||^2 <= target
+// ---------------------------------------------------------------------------
+struct CoreResult {
+    int iters;
+    int status;   // WL_OK (target met), WL_NOCONV, WL_BREAKDOWN
+    double rr;
+};
+
+static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, void *t, void *q,
+                          double target, int maxit) {
+    // r = A^dag (rhs - A x);  p = r
+    check(launch_set_target(k.sc, target, k.s));
+    k.apply(x, t, false, kEpiNone, nullptr, nullptr);
+    k.blas(kOpXmy, const_cast<void *>(rhs), t, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    k.apply(t, r, true, kEpiNone, nullptr, nullptr);
+    k.blas(kOpCopyNorm2, r, p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+    const int chunk = chunk_for(*k.g);
+    int done_it = 0;
+    Scalars h = read_scalars(k.sc, k.s);
+    while (!h.done && done_it < maxit) {
+        const int n = std::min(chunk, maxit - done_it);
+        for (int it = 0; it < n; ++it) {
+            const int *skip = &k.sc->done;
+            k.apply(p, t, false, kEpiCgPap, nullptr, skip);    // t = A p, pap = |t|^2
+            k.apply(t, q, true, kEpiNone, nullptr, skip);      // q = A^dag t
+            k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+            k.blas(kOpCgP, r, p);
+        }
+        h = read_scalars(k.sc, k.s);
+        done_it = h.iter;
+    }
+    CoreResult res;
+    res.iters = h.iter;
+    res.rr = h.rr;
+    res.status = h.done ? h.status : WL_NOCONV;
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab core: iterate on A x = rhs until ||r||^2 <= target
+// ---------------------------------------------------------------------------
+static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *rh, void *p,
+                            void *v, void *sv, void *t, double target, int maxit) {
+    check(launch_set_target(k.sc, target, k.s));
+    k.apply(x, r, false, kEpiNone, nullptr, nullptr);
+    k.blas(kOpXmy, const_cast<void *>(rhs), r, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    k.blas(kOpCopyNorm2, r, rh, nullptr, nullptr, nullptr, nullptr, kEpiBiInit, false);
+    k.blas(kOpZero, p, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    k.blas(kOpZero, v, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    const int chunk = chunk_for(*k.g);
+    Scalars h = read_scalars(k.sc, k.s);
+    while (!h.done && h.iter < maxit) {
+        const int n = std::min(chunk, maxit - h.iter);
+        for (int it = 0; it < n; ++it) {
+            const int *skip = &k.sc->done;
+            k.blas(kOpBiP, r, p, v);                               // p = r + b (p - w v)
+            k.apply(p, v, false, kEpiBiAlpha, rh, skip);           // v = A p, alpha
+            k.blas(kOpBiS, r, v, sv);                              // s = r - alpha v
+            k.apply(sv, t, false, kEpiBiOmega, nullptr, skip);     // t = A s, omega
+            k.blas(kOpBiXR, x, p, sv, t, r, rh, kEpiBiRho);        // x, r, rho, beta
+        }
+        h = read_scalars(k.sc, k.s);
+    }
+    CoreResult res;
+    res.iters = h.iter;
+    res.rr = h.rr;
+    res.status = h.done ? h.status : WL_NOCONV;
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// Even-odd source preparation and reconstruction (in the space's precision)
+// ---------------------------------------------------------------------------
+// bhat_e = b_e + kappa D_eo b_o
+static void eo_source(Space &k, const void *b_full, void *bhat_e) {
+    HopCall c{};
+    c.gauge = k.gauge;
+    c.in[1] = k.par(b_full, 1);
+    c.xs[0] = b_full;
+    c.out[0] = bhat_e;
+    c.first_par = 0; c.npar = 1; c.c = k.kappa; c.dag = false;
+    check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
+}
+
+// x_o = b_o + kappa D_oe x_e   (x_full's even block holds x_e)
+static void eo_reconstruct(Space &k, const void *b_full, void *x_full) {
+    HopCall c{};
+    c.gauge = k.gauge;
+    c.in[0] = x_full;
+    c.xs[1] = k.par(b_full, 1);
+    c.out[1] = k.par(x_full, 1);
+    c.first_par = 1; c.npar = 1; c.c = k.kappa; c.dag = false;
+    check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
+}
+
+// ||b - M x||^2 in FP64 on the full lattice; leaves b - M x in `res`
+static double true_res2(Space &k64full, const void *b, const void *x, void *res) {
+    k64full.apply(x, res, false, kEpiNone, nullptr, nullptr);
+    k64full.blas(kOpXmy, const_cast<void *>(b), res, nullptr, nullptr, nullptr, nullptr,
+                 kEpiNone, false);
+    return read_scalars(k64full.sc, k64full.s).sums[0];
+}
+
+// ---------------------------------------------------------------------------
+// Model cost per Krylov iteration (flops: 1320 per site per hopping term plus
+// 48 per xpay; bytes: compulsory traffic of every kernel)
+// ---------------------------------------------------------------------------
+struct Cost {
+    double flops, bytes;
+};
+
+static Cost apply_cost(const Geom &g, int prec, bool link12, bool eo) {
+    const double V = 2.0 * g.Vh;
+    const double sp = prec == WL_F64 ? 192.0 : 96.0;
+    const double ln = (prec == WL_F64 ? 16.0 : 8.0) * (link12 ? 6 : 9);
+    if (!eo) return {1368.0 * V, V * (2 * sp + 4 * ln)};
+    // two half hops over V/2 sites each; the second adds the xpay read
+    return {(2 * 1320.0 + 48.0) * V / 2, V / 2 * (2 * (2 * sp + 8 * ln) + sp)};
+}
+
+static Cost iter_cost(const Geom &g, int prec, bool link12, bool eo, bool bicg) {
+    const Cost a = apply_cost(g, prec, link12, eo);
+    const double Vs = eo ? g.Vh : 2.0 * g.Vh;
+    const double sp = prec == WL_F64 ? 192.0 : 96.0;
+    // CG: 2 applies + CgXR (4 reads, 2 writes) + CgP (2 reads, 1 write)
+    // BiCGStab: 2 applies (+1 aux read) + BiP (3r 1w) + BiS (2r 1w) + BiXR (5r 2w)
+    const double vec = bicg ? (1 + 4 + 3 + 7) : (6 + 3);
+    return {2 * a.flops, 2 * a.bytes + vec * Vs * sp};
+}
+
+// ---------------------------------------------------------------------------
+// Driver
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxRestarts = 40;
+
+int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = in.g;
+    const bool eo = in.flags & WL_EO;
+    const bool link12 = in.flags & WL_LINK12;
+    const bool mixed = in.flags & WL_MIXED;
+    Workspace ws = carve(g, in.flags, in.work);
+
+    Space full64{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, ws.sc, ws.counter,
+                 ws.partials, nullptr};
+    wl_solve_stats out{};
+    double flops = 0, bytes = 0;
+    int status = WL_NOCONV;
+    try {
+        // counters must start at zero; the scalar block is rewritten by every core
+        check(hipMemsetAsync(ws.counter, 0, 64, in.s));
+        if (!(in.flags & WL_X0))
+            full64.blas(kOpZero, in.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        const double b2 = full64.norm2(in.b);
+        bytes += 2.0 * g.Vh * 192.0;
+        if (!(b2 > 0.0)) {
+            if (!std::isfinite(b2)) {
+                *why = "b is not finite";
+                status = WL_BREAKDOWN;
+            } else {   // b = 0: x = 0 is exact
+                full64.blas(kOpZero, in.x, nullptr, nullptr, nullptr, nullptr, nullptr,
+                            kEpiNone, false);
+                status = WL_OK;
+            }
+            check(hipStreamSynchronize(in.s));
+        } else {
+            const double tol2 = in.tol * in.tol * b2;
+            const Cost tr = apply_cost(g, WL_F64, link12, false);
+            double r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+            flops += tr.flops;
+            bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
+            int total_it = 0, restarts = 0;
+            double best_r2 = r2;
+            int since_best = 0;
+
+            if (!mixed) {
+                // Krylov directly in FP64 on the caller's x (even block for eo)
+                Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, ws.sc, ws.counter,
+                        ws.partials, ws.v64[7]};
+                void *rhs = const_cast<void *>(in.b);
+                if (eo) {
+                    eo_source(k, in.b, ws.v64[5]);
+                    rhs = ws.v64[5];
+                }
+                double mb2 = 0;
+                if (!bicg) {   // ||A^dag rhs||^2 sets the scale of the CG target
+                    k.apply(rhs, ws.v64[2], true, kEpiNone, nullptr, nullptr);
+                    mb2 = k.norm2(ws.v64[2]);
+                }
+                const double rhs2 = bicg ? k.norm2(rhs) : 0.0;
+                double eta = in.tol;
+                while (true) {
+                    if (r2 <= tol2) { status = WL_OK; break; }
+                    if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
+                    if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
+                    CoreResult cr;
+                    const int left = in.maxiter - total_it;
+                    if (!bicg)
+                        cr = cg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2], ws.v64[3],
+                                     eta * eta * mb2, left);
+                    else
+                        cr = bicg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2],
+                                       ws.v64[3], ws.v64[4], ws.v64[6], eta * eta * rhs2, left);
+                    total_it += cr.iters;
+                    const Cost c = iter_cost(g, WL_F64, link12, eo, bicg);
+                    flops += c.flops * cr.iters;
+                    bytes += c.bytes * cr.iters;
+                    if (eo) eo_reconstruct(k, in.b, in.x);
+                    r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+                    flops += tr.flops;
+                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
+                    if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
+                    else ++since_best;
+                    if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
+                    if (r2 <= tol2) { status = WL_OK; break; }
+                    ++restarts;
+                    if (cr.status != WL_BREAKDOWN) {
+                        const double rho = std::sqrt(r2 / b2);
+                        eta = std::max(eta * (in.tol / rho) * 0.5, 1e-17);
+                    }
+                }
+            } else {
+                // FP64 defect correction around FP32 Krylov solves of M e = r
+                Space k{&g, WL_F32, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc, ws.counter,
+                        ws.partials, ws.v32[7]};
+                check(launch_convert_gauge(g, link12, in.gauge, ws.gauge32, in.s));
+                const double delta = 1e-5;
+                while (true) {
+                    if (r2 <= tol2) { status = WL_OK; break; }
+                    if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
+                    if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
+                    // r64 (in v64[6]) -> r32 (v32[5]); e32 (v32[6]) = 0
+                    check(launch_convert_spinor(g, 2, WL_F64, ws.v64[6], WL_F32, ws.v32[5], in.s));
+                    k.eo = false;
+                    k.blas(kOpZero, ws.v32[6], nullptr, nullptr, nullptr, nullptr, nullptr,
+                           kEpiNone, false);
+                    k.eo = eo;
+                    void *rhs = ws.v32[5];
+                    if (eo) {
+                        eo_source(k, ws.v32[5], ws.v32[4]);
+                        rhs = ws.v32[4];
+                    }
+                    const int left = in.maxiter - total_it;
+                    CoreResult cr;
+                    if (!bicg) {
+                        k.apply(rhs, ws.v32[2], true, kEpiNone, nullptr, nullptr);
+                        const double mb2 = k.norm2(ws.v32[2]);
+                        cr = cg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3],
+                                     delta * delta * mb2, left);
+                    } else {
+                        const double rhs2 = k.norm2(rhs);
+                        cr = bicg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2],
+                                       ws.v32[3], ws.v32[8], ws.v32[9], delta * delta * rhs2,
+                                       left);
+                    }
+                    total_it += cr.iters;
+                    const Cost c = iter_cost(g, WL_F32, link12, eo, bicg);
+                    flops += c.flops * cr.iters;
+                    bytes += c.bytes * cr.iters;
+                    if (eo) eo_reconstruct(k, ws.v32[5], ws.v32[6]);
+                    check(launch_accum_f32(g, 2, ws.v32[6], in.x, in.s));
+                    r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+                    flops += tr.flops;
+                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
+                    ++restarts;
+                    if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
+                    else ++since_best;
+                    if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
+                }
+            }
+            out.iterations = total_it;
+            out.restarts = restarts;
+            out.true_res = std::sqrt(r2 / b2);
+        }
+        check(hipStreamSynchronize(in.s));
+    } catch (const Fail &f) {
+        *why = std::string("HIP error in solver: ") + hipGetErrorString(f.err);
+        hipStreamSynchronize(in.s);
+        status = WL_EHIP;
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    out.status = status;
+    out.seconds = std::chrono::duration<double>(t1 - t0).count();
+    out.flops = flops;
+    out.bytes = bytes;
+    if (st) *st = out;
+    return status;
+}
+
+}  // namespace wl

@@ -1,0 +1,262 @@
+"""Python binding of ``libwilson.so`` (the C ABI declared in include/wilson.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. torch tensors serve as device buffers and torch streams as HIP
+streams. Packed fields are plain ``torch.uint8`` tensors of the byte size the
+library reports; the layout is the library's even-odd layout (wilson.h).
+
+Importing this module raises if the library is not built: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwilson.so")
+
+# flags (wilson.h)
+F64 = 0x0
+F32 = 0x1
+LINK18 = 0x0
+LINK12 = 0x4
+DAG = 0x8
+HOP = 0x10
+EO = 0x20
+MIXED = 0x40
+X0 = 0x80
+
+OK, NOCONV, BREAKDOWN, STAGNATED = 0, 1, 2, 3
+EINVAL, EWORKSPACE, EHIP = -1, -2, -3
+STATUS_NAMES = {0: "OK", 1: "NOCONV", 2: "BREAKDOWN", 3: "STAGNATED",
+                -1: "EINVAL", -2: "EWORKSPACE", -3: "EHIP"}
+
+ANTIPERIODIC_T = (1.0, 1.0, 1.0, -1.0)
+
+# exported symbols, in the order of wilson.h
+SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
+           "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor",
+           "wilson_dslash", "wilson_dslash_eo", "wl_workspace_bytes",
+           "solve_cg", "solve_bicgstab")
+
+
+class WilsonError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("op_applies", ctypes.c_int32),
+                ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwilson.so is not built (%s); run "
+                          "`python -m paper_1112_5280_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U32, I32, D, SZ = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32,
+                          ctypes.c_double, ctypes.c_size_t)
+    lib.wl_version.restype = ctypes.c_char_p
+    lib.wl_last_error.restype = ctypes.c_char_p
+    lib.wl_spinor_bytes.argtypes = [P, U32, I32]
+    lib.wl_spinor_bytes.restype = SZ
+    lib.wl_gauge_bytes.argtypes = [P, U32]
+    lib.wl_gauge_bytes.restype = SZ
+    for f in (lib.wl_pack_gauge, lib.wl_pack_spinor, lib.wl_unpack_spinor):
+        f.argtypes = [P, P, P, U32, P]
+        f.restype = ctypes.c_int
+    lib.wilson_dslash.argtypes = [P, P, P, P, D, P, U32, P]
+    lib.wilson_dslash.restype = ctypes.c_int
+    lib.wilson_dslash_eo.argtypes = [P, P, P, P, D, P, I32, U32, P]
+    lib.wilson_dslash_eo.restype = ctypes.c_int
+    lib.wl_workspace_bytes.argtypes = [P, U32, I32]
+    lib.wl_workspace_bytes.restype = SZ
+    for f in (lib.solve_cg, lib.solve_bicgstab):
+        f.argtypes = [P, P, P, P, D, P, D, I32, U32, P, SZ,
+                      ctypes.POINTER(SolveStats), P]
+        f.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+# ---------------------------------------------------------------------------
+def _dims(dims):
+    return (ctypes.c_int32 * 4)(*[int(d) for d in dims])
+
+
+def _phases(phases):
+    ph = np.asarray(phases, dtype=np.complex128).reshape(4)
+    flat = np.stack([ph.real, ph.imag], axis=1).reshape(-1)
+    return (ctypes.c_double * 8)(*flat.tolist())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(code, what):
+    if code < 0:
+        raise WilsonError(code, "%s: %s" % (what, last_error()))
+    return code
+
+
+def version() -> str:
+    return lib.wl_version().decode()
+
+
+def last_error() -> str:
+    return lib.wl_last_error().decode()
+
+
+def spinor_bytes(dims, flags=F64, nparity=2) -> int:
+    n = lib.wl_spinor_bytes(_dims(dims), flags, nparity)
+    if n == 0:
+        raise WilsonError(EINVAL, "invalid dims/flags for a spinor: %s" % (dims,))
+    return int(n)
+
+
+def gauge_bytes(dims, flags=F64) -> int:
+    n = lib.wl_gauge_bytes(_dims(dims), flags)
+    if n == 0:
+        raise WilsonError(EINVAL, "invalid dims/flags for a gauge field: %s" % (dims,))
+    return int(n)
+
+
+def workspace_bytes(dims, flags=F64, nrhs=1) -> int:
+    return int(lib.wl_workspace_bytes(_dims(dims), flags, nrhs))
+
+
+def empty_spinor(dims, flags=F64, nparity=2, device="cuda"):
+    return torch.empty(spinor_bytes(dims, flags, nparity), dtype=torch.uint8, device=device)
+
+
+def zeros_spinor(dims, flags=F64, nparity=2, device="cuda"):
+    return torch.zeros(spinor_bytes(dims, flags, nparity), dtype=torch.uint8, device=device)
+
+
+def parity_block(packed, dims, flags, parity):
+    """View of one parity block (a half field) of a packed full spinor."""
+    n = spinor_bytes(dims, flags, 1)
+    return packed[parity * n:(parity + 1) * n]
+
+
+def _canon_device(a, shape, device):
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+    a = a.to(device=device, dtype=torch.complex128).contiguous()
+    if tuple(a.shape) != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, tuple(a.shape)))
+    return a
+
+
+def pack_gauge(U, dims, flags=F64, out=None, stream=None, device="cuda"):
+    """Canonical complex128 U[V,4,3,3] (numpy or torch) -> packed device field."""
+    V = int(np.prod(dims))
+    Ud = _canon_device(U, (V, 4, 3, 3), device)
+    if out is None:
+        out = torch.empty(gauge_bytes(dims, flags), dtype=torch.uint8, device=device)
+    _check(lib.wl_pack_gauge(_ptr(Ud), _ptr(out), _dims(dims), flags, _stream(stream)),
+           "wl_pack_gauge")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return out
+
+
+def pack_spinor(psi, dims, flags=F64, out=None, stream=None, device="cuda"):
+    """Canonical complex128 psi[V,4,3] (numpy or torch) -> packed full spinor."""
+    V = int(np.prod(dims))
+    pd = _canon_device(psi, (V, 4, 3), device)
+    if out is None:
+        out = torch.empty(spinor_bytes(dims, flags, 2), dtype=torch.uint8, device=device)
+    _check(lib.wl_pack_spinor(_ptr(pd), _ptr(out), _dims(dims), flags, _stream(stream)),
+           "wl_pack_spinor")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return out
+
+
+def unpack_spinor(packed, dims, flags=F64, stream=None):
+    """Packed full spinor -> canonical complex128 torch tensor [V,4,3] on device."""
+    V = int(np.prod(dims))
+    out = torch.empty((V, 4, 3), dtype=torch.complex128, device=packed.device)
+    _check(lib.wl_unpack_spinor(_ptr(packed), _ptr(out), _dims(dims), flags,
+                                _stream(stream)), "wl_unpack_spinor")
+    return out
+
+
+def wilson_dslash(gauge, inp, out, dims, kappa, phases=ANTIPERIODIC_T, flags=F64,
+                  stream=None):
+    """out = M in (default), D_W in (HOP), or the adjoint (DAG); asynchronous."""
+    return _check(lib.wilson_dslash(_ptr(gauge), _ptr(inp), _ptr(out), _dims(dims),
+                                    float(kappa), _phases(phases), flags, _stream(stream)),
+                  "wilson_dslash")
+
+
+def wilson_dslash_eo(gauge, inp, out, dims, kappa, out_parity, phases=ANTIPERIODIC_T,
+                     flags=F64, stream=None):
+    """HOP: out_p = D_{p,1-p} in_{1-p}; default: out_p = Mhat_p in_p (half fields)."""
+    return _check(lib.wilson_dslash_eo(_ptr(gauge), _ptr(inp), _ptr(out), _dims(dims),
+                                       float(kappa), _phases(phases), int(out_parity),
+                                       flags, _stream(stream)), "wilson_dslash_eo")
+
+
+def _solve(fn, name, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work, stream):
+    need = workspace_bytes(dims, flags)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=b.device)
+    st = SolveStats()
+    code = fn(_ptr(gauge), _ptr(b), _ptr(x), _dims(dims), float(kappa), _phases(phases),
+              float(tol), int(maxiter), flags, _ptr(work), work.numel(), ctypes.byref(st),
+              _stream(stream))
+    _check(code, name)
+    d = st.as_dict()
+    d["status_name"] = STATUS_NAMES.get(code, "?")
+    if code != OK:
+        d["message"] = last_error()
+    return d
+
+
+def solve_cg(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000,
+             flags=F64, work=None, stream=None):
+    """CGNR solve of M x = b (packed FP64 b, x); returns the stats dict."""
+    return _solve(lib.solve_cg, "solve_cg", gauge, b, x, dims, kappa, phases, tol, maxiter,
+                  flags, work, stream)
+
+
+def solve_bicgstab(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
+                   maxiter=100000, flags=F64, work=None, stream=None):
+    """BiCGStab solve of M x = b (packed FP64 b, x); returns the stats dict."""
+    return _solve(lib.solve_bicgstab, "solve_bicgstab", gauge, b, x, dims, kappa, phases,
+                  tol, maxiter, flags, work, stream)
+
+
+@dataclass
+class Problem:
+    """A lattice problem resident on the device (packed gauge field)."""
+    dims: tuple
+    kappa: float
+    gauge: torch.Tensor
+    flags: int = F64
+    phases: tuple = ANTIPERIODIC_T

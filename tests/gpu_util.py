@@ -1,0 +1,45 @@
+"""Helpers shared by the GPU parity tests (test infrastructure)."""
+import numpy as np
+import torch
+
+# Bars from the problem statement: FP64 operators agree with the FP64 oracle to
+# 1e-13 relative; FP32 to 1e-6. Both the field-norm ratio and the max-abs ratio
+# must meet them (sites can be near zero, so no per-site relative error).
+TOL = {0x0: 1e-13, 0x1: 1e-6}
+
+
+def errs(got, want):
+    got = np.asarray(got).reshape(-1)
+    want = np.asarray(want).reshape(-1)
+    d = got - want
+    return (float(np.linalg.norm(d) / np.linalg.norm(want)),
+            float(np.abs(d).max() / np.abs(want).max()))
+
+
+def assert_close(got, want, tol, what=""):
+    n, m = errs(got, want)
+    assert n <= tol and m <= tol, "%s: rel-norm %.3e, rel-max %.3e > %.1e" % (what, n, m, tol)
+
+
+def sync():
+    torch.cuda.synchronize()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def half_to_canon(w, half, dims, flags, parity):
+    """Unpack one packed parity block into a canonical [V,4,3] array (zeros on
+    the other parity)."""
+    prec = flags & 0x3
+    full = w.zeros_spinor(dims, prec, 2)
+    w.parity_block(full, dims, prec, parity).copy_(half)
+    return to_np(w.unpack_spinor(full, dims, prec))
+
+
+def parity_of_sites(dims):
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    return ((x + y + z + t) % 2).reshape(-1)

@@ -1,0 +1,92 @@
+"""The C-ABI library loads, exports every symbol include/wilson.h declares, and
+its host-side argument checks work (no GPU needed: nothing here launches)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wilson.h")
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_1112_5280_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1112_5280_amd import wilson
+    return wilson
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", text, flags=re.M)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("wilson_dslash", "wilson_dslash_eo", "solve_cg", "solve_bicgstab"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(w):
+    names = declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", w.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(names) == set(w.SYMBOLS)
+    for n in names:
+        assert hasattr(w.lib, n)
+
+
+def test_sizes(w):
+    d = (4, 4, 4, 4)              # Vh = 128 = S
+    assert w.spinor_bytes(d, w.F64, 1) == 128 * 12 * 16
+    assert w.spinor_bytes(d, w.F32, 2) == 2 * 128 * 12 * 8
+    assert w.gauge_bytes(d, w.F64) == 2 * 4 * 9 * 16 * 128
+    assert w.gauge_bytes(d, w.F32 | w.LINK12) == 2 * 4 * 6 * 8 * 128
+    d = (6, 4, 6, 10)             # Vh = 720 -> S = 768
+    assert w.spinor_bytes(d, w.F64, 1) == 768 * 12 * 16
+    assert w.workspace_bytes(d, w.MIXED) > w.workspace_bytes(d, 0) > 0
+    assert w.lib.wl_spinor_bytes(w._dims((3, 4, 4, 4)), 0, 2) == 0
+    assert w.lib.wl_gauge_bytes(w._dims((4, 4, 4, 4)), 0x3) == 0
+
+
+def _p(v):
+    return ctypes.c_void_p(v)
+
+
+def test_argument_checks_return_einval(w):
+    d, ph = w._dims((4, 4, 4, 4)), w._phases(w.ANTIPERIODIC_T)
+    lib = w.lib
+    assert lib.wilson_dslash(None, None, None, w._dims((4, 4, 4, 3)), 0.1, ph, 0, None) == -1
+    assert "even" in w.last_error()
+    assert lib.wilson_dslash(_p(8), _p(16), _p(16), d, 0.1, ph, 0, None) == -1
+    assert "alias" in w.last_error()
+    assert lib.wilson_dslash(_p(8), _p(16), _p(32), d, 0.1,
+                             w._phases((1, 1, 1, 0.5)), 0, None) == -1
+    assert lib.wilson_dslash(_p(8), _p(16), _p(32), d, float("nan"), ph, 0, None) == -1
+    assert lib.wilson_dslash(_p(8), _p(16), _p(32), d, 0.1, ph, 1 << 20, None) == -1
+    assert lib.wilson_dslash_eo(_p(8), _p(16), _p(32), d, 0.1, ph, 2, 0, None) == -1
+    assert lib.wl_pack_spinor(_p(8), _p(8), d, 0, None) == -1
+
+
+def test_solver_argument_checks(w):
+    d, ph = w._dims((4, 4, 4, 4)), w._phases(w.ANTIPERIODIC_T)
+    st = w.SolveStats()
+    call = lambda **k: w.lib.solve_cg(
+        _p(8), _p(16), _p(k.get("x", 24)), k.get("dims", d), 0.1, ph, k.get("tol", 1e-10),
+        k.get("maxiter", 10), k.get("flags", 0), _p(32), k.get("work", 1 << 30),
+        ctypes.byref(st), None)
+    assert call(work=10) == -2 and "workspace" in w.last_error()
+    assert call(x=16) == -1                       # b aliases x
+    assert call(tol=0.0) == -1
+    assert call(maxiter=0) == -1
+    assert call(flags=w.F32) == -1                # solver buffers are FP64
+    assert call(flags=w.DAG) == -1
+    assert call(dims=w._dims((4, 4, 4, 5))) == -1

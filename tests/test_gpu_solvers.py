@@ -1,0 +1,149 @@
+"""GPU solves: every solution must reach ||b - M x|| / ||b|| <= 1e-10 with the
+residual recomputed by the FP64 CPU oracle, and agree with the oracle's own
+solution within the conditioning bound. Failure paths return their documented
+status without hanging.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_5280_amd import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_1112_5280_amd import wilson
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return wilson
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    """4^4, Haar links (seed 0), kappa = 0.12, Gaussian source (seed 1)."""
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_haar(dims, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    xs, st = oracle.cgnr(U, b, dims, 0.12, tol=1e-13)
+    assert st["status"] == 0
+    return dims, U, b, xs
+
+
+SOLVES = [
+    ("cg", 0x0), ("cg", 0x20), ("cg", 0x40), ("cg", 0x60), ("cg", 0x4 | 0x20),
+    ("bicgstab", 0x0), ("bicgstab", 0x20), ("bicgstab", 0x40), ("bicgstab", 0x60),
+    ("bicgstab", 0x4 | 0x60),
+]
+
+
+def _name(s):
+    solver, f = s
+    parts = [solver]
+    parts.append("eo" if f & 0x20 else "full")
+    if f & 0x40:
+        parts.append("mixed")
+    if f & 0x4:
+        parts.append("link12")
+    return "-".join(parts)
+
+
+def _solve(w, solver, G, B, X, dims, kappa, flags, maxiter=20000):
+    fn = w.solve_cg if solver == "cg" else w.solve_bicgstab
+    return fn(G, B, X, dims, kappa, tol=1e-10, maxiter=maxiter, flags=flags)
+
+
+@pytest.mark.parametrize("solve", SOLVES, ids=[_name(s) for s in SOLVES])
+def test_config1_solves(w, cfg1, solve):
+    dims, U, b, xs = cfg1
+    solver, flags = solve
+    kappa = 0.12
+    G = w.pack_gauge(U, dims, flags & 0x4)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    st = _solve(w, solver, G, B, X, dims, kappa, flags)
+    assert st["status"] == 0, st
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    res = oracle.true_residual(U, b, x, dims, kappa)
+    assert res <= 1e-10 and st["true_res"] <= 1e-10, (res, st)
+    assert abs(res - st["true_res"]) <= 1e-12
+    cond = (1 + 8 * kappa) / (1 - 8 * kappa)     # bound for kappa < 1/8
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= cond * 1.2e-10
+
+
+@pytest.mark.parametrize("solve", [("cg", 0x20), ("cg", 0x60), ("bicgstab", 0x20),
+                                   ("bicgstab", 0x60)],
+                         ids=["cg-eo", "cg-eo-mixed", "bicgstab-eo", "bicgstab-eo-mixed"])
+def test_smooth_field_solves(w, solve):
+    """8^3 x 16, exp(i eps H) links with eps = 0.3, kappa = 0.15 (past the
+    spectrum's crossing of Re = 0 for these fields: CG must converge; BiCGStab
+    may stagnate and then must say so)."""
+    dims = (8, 8, 8, 16)
+    kappa = 0.15
+    U = synth.gauge_smooth(dims, 0.3, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    solver, flags = solve
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    st = _solve(w, solver, G, B, X, dims, kappa, flags, maxiter=40000)
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    res = oracle.true_residual(U, b, x, dims, kappa)
+    assert abs(res - st["true_res"]) <= 1e-9 * max(1.0, res)
+    if solver == "cg":
+        assert st["status"] == 0 and res <= 1e-10, st
+    else:
+        assert st["status"] in (0, 3), st
+        if st["status"] == 0:
+            assert res <= 1e-10
+
+
+def test_free_field_point_source(w):
+    """Unit links, point source: the GPU solution satisfies the oracle's M."""
+    dims = (4, 4, 4, 8)
+    kappa = 0.124
+    U = synth.gauge_unit(dims)
+    b = synth.point_source(dims, 37, 2, 1)
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    st = w.solve_cg(G, B, X, dims, kappa, flags=w.EO)
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    assert st["status"] == 0
+    assert oracle.true_residual(U, b, x, dims, kappa) <= 1e-10
+
+
+def test_warm_start_and_determinism(w, cfg1):
+    dims, U, b, xs = cfg1
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X1, X2 = w.empty_spinor(dims), w.empty_spinor(dims)
+    w.solve_cg(G, B, X1, dims, 0.12, flags=w.EO)
+    w.solve_cg(G, B, X2, dims, 0.12, flags=w.EO)
+    assert torch.equal(X1, X2)
+    st = w.solve_cg(G, B, X1, dims, 0.12, flags=w.EO | w.X0)   # already converged
+    assert st["status"] == 0 and st["iterations"] == 0
+
+
+def test_failure_statuses(w, cfg1):
+    dims, U, b, _ = cfg1
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    st = w.solve_cg(G, B, X, dims, 0.12, maxiter=1)
+    assert st["status"] == w.NOCONV
+    assert np.isfinite(gu.to_np(w.unpack_spinor(X, dims))).all()
+    bn = b.copy()
+    bn[3, 1, 2] = np.nan
+    st = w.solve_bicgstab(G, w.pack_spinor(bn, dims), X, dims, 0.12)
+    assert st["status"] == w.BREAKDOWN
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(w.WilsonError) as e:
+        w.solve_cg(G, B, X, dims, 0.12, work=small)
+    assert e.value.code == w.EWORKSPACE
+    zero = w.pack_spinor(np.zeros_like(b), dims)
+    st = w.solve_cg(G, zero, X, dims, 0.12)
+    assert st["status"] == 0
+    assert not gu.to_np(w.unpack_spinor(X, dims)).any()
