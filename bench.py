@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the Wilson-Dirac hot path on one MI355X.
+
+Workload (default): the 32^3 x 64 lattice (2,097,152 sites), links
+exp(i eps H) with eps = 0.35 (seed 0), kappa = 0.155, Gaussian source (seed 1),
+antiperiodic time. One step = pack the resident source, an even-odd
+preconditioned mixed-precision CG solve (FP32 Krylov iterations inside FP64
+defect correction) to ||b - M x|| / ||b|| <= 1e-10 recomputed in FP64, and
+unpack the solution.
+
+Printed: one JSON line. ``value`` is the whole-step throughput in algorithmic
+(compulsory) GB/s -- the library's per-kernel byte model summed over the step,
+divided by the step's wall time. ``roofline`` describes the dominant kernel
+(the FP32 even-odd hopping term) timed with HIP events on the stream it runs
+on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice.
+Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
+and every Dslash variant's GB/s and GFLOP/s.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: dims, kappa, eps
+    "32^3x64": ((32, 32, 32, 64), 0.155, 0.35),
+    "16^3x32": ((16, 16, 16, 32), 0.15, 0.30),
+    "8^3x16": ((8, 8, 8, 16), 0.15, 0.30),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="32^3x64", choices=sorted(WORKLOADS))
+    ap.add_argument("--link12", action="store_true", help="12-real link storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--kernel-launches", type=int, default=50)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_kernel(fn, n, torch):
+    """Average duration of fn() over n launches, HIP events on the launch stream."""
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(n):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / n
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    from paper_1112_5280_amd import synth
+    from paper_1112_5280_amd import wilson as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dims, kappa, eps = WORKLOADS[args.workload]
+    V = synth.volume(dims)
+    Vh = V // 2
+    link = w.LINK12 if args.link12 else w.LINK18
+    t = time.time()
+    U = synth.gauge_smooth(dims, eps, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    log("inputs generated in %.1f s" % (time.time() - t))
+
+    G64 = w.pack_gauge(U, dims, w.F64 | link)
+    b_dev = torch.from_numpy(b).to("cuda")
+    B = w.empty_spinor(dims)
+    X = w.empty_spinor(dims)
+    x_dev = torch.empty_like(b_dev)
+    flags = w.EO | w.MIXED | link
+    work = torch.empty(w.workspace_bytes(dims, flags), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    sp = w._stream(s)
+    d4 = w._dims(dims)
+
+    def step():
+        w._check(w.lib.wl_pack_spinor(w._ptr(b_dev), w._ptr(B), d4, w.F64, sp), "pack")
+        st = w.solve_cg(G64, B, X, dims, kappa, tol=1e-10, maxiter=200000, flags=flags,
+                        work=work, stream=s)
+        w._check(w.lib.wl_unpack_spinor(w._ptr(X), w._ptr(x_dev), d4, w.F64, sp), "unpack")
+        return st
+
+    for _ in range(args.warmup):
+        st = step()
+        log("warmup solve: status %s, %d iterations, %d outer, true residual %.2e, %.3f s"
+            % (st["status_name"], st["iterations"], st["restarts"], st["true_res"],
+               st["seconds"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    for st in stats:
+        assert st["status"] == 0 and st["true_res"] <= 1e-10, st
+    pack_bytes = 2 * V * (192 + 192)           # canonical <-> packed, both ways
+    step_bytes = float(np.mean([st["bytes"] for st in stats])) + pack_bytes
+    step_flops = float(np.mean([st["flops"] for st in stats]))
+    value = step_bytes / (ms / 1e3) / 1e9
+
+    # FP64 solve of the same system on the same GPU, for the mixed-vs-FP64 comparison
+    fp64 = None
+    if not args.no_fp64_compare:
+        X64 = w.empty_spinor(dims)
+        w64 = torch.empty(w.workspace_bytes(dims, w.EO | link), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st64 = w.solve_cg(G64, B, X64, dims, kappa, tol=1e-10, maxiter=200000,
+                          flags=w.EO | link, work=w64, stream=s)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        x64 = w.unpack_spinor(X64, dims)
+        diff = float(torch.linalg.vector_norm(x64 - x_dev) / torch.linalg.vector_norm(x64))
+        fp64 = {"seconds": dt, "iterations": st64["iterations"], "status": st64["status_name"],
+                "true_res": st64["true_res"], "mixed_speedup": dt / (ms / 1e3),
+                "mixed_vs_fp64_solution_rel_diff": diff}
+        del X64, w64, x64
+
+    # Dslash variants, each timed over a run of launches (HIP events)
+    variants = {}
+    n = args.kernel_launches
+    for prec, pname in ((w.F64, "f64"), (w.F32, "f32")):
+        for lk, lname in ((w.LINK18, "18"), (w.LINK12, "12")):
+            G = w.pack_gauge(U, dims, prec | lk)
+            P = w.pack_spinor(b, dims, prec)
+            O = w.empty_spinor(dims, prec)
+            Oh = w.empty_spinor(dims, prec, 1)
+            sb = 192 if prec == w.F64 else 96
+            lb = (16 if prec == w.F64 else 8) * (6 if lk else 9)
+            f = prec | lk
+            tm = time_kernel(lambda: w.wilson_dslash(G, P, O, dims, kappa, flags=f, stream=s),
+                             n, torch)
+            variants["M_%s_%s" % (pname, lname)] = {
+                "us": tm * 1e6, "GBs": V * (2 * sb + 4 * lb) / tm / 1e9,
+                "GFLOPs": 1368 * V / tm / 1e9}
+            te = time_kernel(lambda: w.wilson_dslash_eo(
+                G, w.parity_block(P, dims, prec, 0), Oh, dims, kappa, 1, flags=f | w.HOP,
+                stream=s), n, torch)
+            variants["Deo_%s_%s" % (pname, lname)] = {
+                "us": te * 1e6, "GBs": Vh * (2 * sb + 8 * lb) / te / 1e9,
+                "GFLOPs": 1320 * Vh / te / 1e9}
+            del G, P, O, Oh
+    torch.cuda.empty_cache()
+
+    # roofline of the dominant kernel of the step: the FP32 even-odd hop
+    dom = "Deo_f32_%s" % ("12" if args.link12 else "18")
+    lb = 8 * (6 if args.link12 else 9)
+    per_launch = Vh * (2 * 96 + 8 * lb)
+    ach = variants[dom]["GBs"]
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "hop_kernel<float,%d,false,false,0> (even-odd hop, FP32)"
+                          % (6 if args.link12 else 9),
+                "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ncores = len(os.sched_getaffinity(0))
+        oracle.set_threads(ncores)
+        nrep = 2
+        oracle.mop(U, b, dims, kappa)        # warm-up
+        t = time.perf_counter()
+        for _ in range(nrep):
+            oracle.mop(U, b, dims, kappa)
+        dt = (time.perf_counter() - t) / nrep
+        cpu = {"value": 960.0 * V / dt / 1e9, "unit": "GB/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": "%d FP64 M applies of the oracle on the %s lattice; %.2f s each, "
+                         "%.2f GFLOP/s at 1368 flop/site; GB/s counts 960 B/site like the "
+                         "GPU M" % (nrep, args.workload, dt, 1368.0 * V / dt / 1e9),
+               "seconds_per_apply": dt}
+
+    out = {
+        "metric": "Dslash GB/s (% HBM peak) & GFLOP/s; solves/s + p99 latency, mixed vs FP64",
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "wilson eo-CG mixed-precision solve %s" % args.workload,
+                   "lattice": list(dims), "kappa": kappa, "links": "exp(i*%.2f*H), seed 0" % eps,
+                   "link_storage": "12-real" if args.link12 else "18-real",
+                   "tol": 1e-10, "parallelism": "single GPU"},
+        "pct_hbm_peak": 100.0 * value / HBM_PEAK_GBS,
+        "solves_per_s": 1e3 / ms,
+        "gflops": step_flops / (ms / 1e3) / 1e9,
+        "iterations": int(np.mean([st["iterations"] for st in stats])),
+        "outer_corrections": int(np.mean([st["restarts"] for st in stats])),
+        "true_res": max(st["true_res"] for st in stats),
+        "fp64_solve": fp64,
+        "dslash_variants": variants,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -185,6 +185,8 @@ struct Space {
 // large enough to hide the readback.
 static int chunk_for(const Geom &g) { return g.Vh >= (1 << 18) ? 4 : 16; }
 
+constexpr int kStallWindow = 2000;
+
 // ---------------------------------------------------------------------------
 // CGNR core: iterate on A^dag A x = A^dag rhs until ||r||^2 <= target
 // ---------------------------------------------------------------------------
@@ -237,6 +239,11 @@ static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *r
     k.blas(kOpZero, v, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
     const int chunk = chunk_for(*k.g);
     Scalars h = read_scalars(k.sc, k.s);
+    // BiCGStab's residual is not monotone; it has stagnated when its best value
+    // has not improved by 1% within kStallWindow iterations.
+    double best = h.rr;
+    int best_it = 0;
+    bool stalled = false;
     while (!h.done && h.iter < maxit) {
         const int n = std::min(chunk, maxit - h.iter);
         for (int it = 0; it < n; ++it) {
@@ -248,11 +255,18 @@ static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *r
             k.blas(kOpBiXR, x, p, sv, t, r, rh, kEpiBiRho);        // x, r, rho, beta
         }
         h = read_scalars(k.sc, k.s);
+        if (h.rr < 0.99 * best) {
+            best = h.rr;
+            best_it = h.iter;
+        } else if (h.iter - best_it > kStallWindow) {
+            stalled = true;
+            break;
+        }
     }
     CoreResult res;
     res.iters = h.iter;
     res.rr = h.rr;
-    res.status = h.done ? h.status : WL_NOCONV;
+    res.status = h.done ? h.status : (stalled ? WL_STAGNATED : WL_NOCONV);
     return res;
 }
 
