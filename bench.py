@@ -53,19 +53,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1112_5280_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(link12):
+    """Bytes per launch of the roofline kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when
+    the summary is for another kernel or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "hop_f32_eo_32x64_pmc.json")
+    if link12 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        pm = json.load(f)
+    if pm.get("source_hash") != kernel_source_hash():
+        return None
+    return pm["traffic_bytes_per_launch"]
+
+
 def time_kernel(fn, n, torch):
-    """Average duration of fn() over n launches, HIP events on the launch stream."""
+    """Average duration of one launch of fn(), in seconds: a pair of HIP events
+    around each of n launches on the launch stream (gaps between launches are
+    not counted, as in a profiler's per-dispatch durations)."""
     s = torch.cuda.current_stream()
     fn()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(n):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for e0, e1 in ev:
+        e0.record(s)
         fn()
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / n
+        e1.record(s)
+    ev[-1][1].synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3 / n
 
 
 def main():
@@ -169,16 +195,27 @@ def main():
             del G, P, O, Oh
     torch.cuda.empty_cache()
 
+    # achievable bandwidth of a plain device copy of known size (also the
+    # reference the profiler's byte counters are scaled by)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    tc = time_kernel(lambda: dst.copy_(src), 20, torch)
+    copy = {"bytes_moved": 2 * nbytes, "us": tc * 1e6, "GBs": 2 * nbytes / tc / 1e9}
+    del src, dst
+
     # roofline of the dominant kernel of the step: the FP32 even-odd hop
     dom = "Deo_f32_%s" % ("12" if args.link12 else "18")
     lb = 8 * (6 if args.link12 else 9)
     per_launch = Vh * (2 * 96 + 8 * lb)
     ach = variants[dom]["GBs"]
+    traffic = profiled_traffic(args.link12) if args.workload == "32^3x64" else None
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "hop_kernel<float,%d,false,false,0> (even-odd hop, FP32)"
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "wl::hop_kernel<float, %d, false, false, 0> (even-odd hop, FP32)"
                           % (6 if args.link12 else 9),
-                "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"]}
+                "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
+                "frac_of_copy": ach / copy["GBs"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -223,6 +260,7 @@ def main():
         "true_res": max(st["true_res"] for st in stats),
         "fp64_solve": fp64,
         "dslash_variants": variants,
+        "device_copy": copy,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -35,13 +35,17 @@
  *   spinor (full field): [parity][chunk][S], parity 0 = even block first;
  *     a half field (one parity) is one [chunk][S] block, wl_spinor_bytes(.., 1).
  *     FP64: 12 chunks of double2 (one complex each, index spin*3 + colour);
- *     FP32: 6 chunks of float4 (two consecutive complex components each).
+ *     FP32: 6 chunks of float4 (two consecutive complex components each);
+ *     FP16 (WL_F16S): 3 chunks of 8 binary16 values holding psi/s, where
+ *     s = max |real or imaginary component| of the site, followed by the S
+ *     FP32 scales s of the block (52 bytes per site).
  *   gauge: [parity][mu][chunk][S]; link U_mu(x) stored at the parity and
  *     checkerboard index of x. 18-real: the 9 complex entries, row-major;
  *     12-real (WL_LINK12): rows 0 and 1 only, row 2 = conj(row0 x row1) is
  *     rebuilt in the kernel (exact for det U = 1). FP64: one complex per
  *     double2 chunk; FP32: float2 per complex (18-real), float4 per complex
- *     pair (12-real).
+ *     pair (12-real); FP16: binary16 pairs per complex (18-real) or quads
+ *     per complex pair (12-real), unscaled (|U_ij| <= 1).
  *   Checkerboard index of site s (with parity (x+y+z+t) & 1) is s / 2.
  *   Padding entries (checkerboard index >= Vh) are never read or written by
  *   the operators.
@@ -64,13 +68,17 @@ extern "C" {
 /* ---- flags --------------------------------------------------------------- */
 #define WL_F64        0x0u   /* storage and arithmetic precision: FP64        */
 #define WL_F32        0x1u   /* FP32                                          */
+#define WL_F16S       0x2u   /* FP16 storage (spinors scaled per site), FP32
+                                arithmetic                                    */
 #define WL_PREC_MASK  0x3u
 #define WL_LINK18     0x0u   /* links stored as 18 reals                      */
 #define WL_LINK12     0x4u   /* links stored as 12 reals (rows 0, 1)          */
 #define WL_DAG        0x8u   /* apply the adjoint (M^dag, D_W^dag, Mhat^dag)  */
 #define WL_HOP        0x10u  /* return the hopping term only (no 1 - kappa.)  */
 #define WL_EO         0x20u  /* solvers: even-odd (Schur) preconditioning     */
-#define WL_MIXED      0x40u  /* solvers: FP32 inner solve, FP64 outer loop    */
+#define WL_MIXED      0x40u  /* solvers: low-precision inner Krylov iterations
+                                (WL_F32, the default, or WL_F16S) inside an
+                                FP64 outer loop                               */
 #define WL_X0         0x80u  /* solvers: x holds the initial guess            */
 
 /* ---- status codes -------------------------------------------------------- */
@@ -86,7 +94,7 @@ typedef struct {
     int32_t status;           /* same value the solver returned               */
     int32_t iterations;       /* Krylov iterations over all restarts          */
     int32_t restarts;         /* true-residual restarts / outer corrections   */
-    int32_t op_applies;       /* operator applications (M, Mhat or adjoint)   */
+    int32_t reliable_updates; /* FP64 refreshes inside mixed-precision CG     */
     double true_res;          /* ||b - M x|| / ||b||, FP64, full lattice      */
     double seconds;           /* wall time of the solve                       */
     double flops;             /* model flops (1320/site per D_W)              */
@@ -153,7 +161,13 @@ size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
  *   solve_bicgstab: BiCGStab on M.
  * With WL_EO both run on the Schur system Mhat_e x_e = b_e + kappa D_eo b_o and
  * reconstruct x_o = b_o + kappa D_oe x_e. With WL_MIXED the Krylov iterations
- * run in FP32 (FP32 links and spinors) inside an FP64 defect-correction loop.
+ * run in low precision -- FP32 (WL_F32 or no precision bits) or FP16 storage
+ * with FP32 arithmetic (WL_F16S) -- on a copy of the links made at the start
+ * of the solve: CG keeps one Krylov sequence and refreshes the FP64 solution
+ * and residual whenever the low-precision residual has dropped by 10x (5x for
+ * FP16) ("reliable updates"); BiCGStab restarts its low-precision solve of
+ * M e = r from each FP64 residual (defect correction). FP64 is used only for
+ * the solution, the residuals, and the global reductions.
  * `gauge` is the packed FP64 gauge field (link format per flags); `b` and `x`
  * are packed FP64 full spinors; x is the initial guess with WL_X0, otherwise
  * it is overwritten from zero. `work` is device scratch of at least

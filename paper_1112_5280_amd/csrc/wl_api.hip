@@ -38,12 +38,15 @@ bool make_geom(const int32_t dims[4], Geom *g, std::string *why) {
     return true;
 }
 
+static size_t complex_bytes(int prec) { return prec == WL_F64 ? 16 : prec == WL_F32 ? 8 : 4; }
+
 size_t spinor_block_bytes(const Geom &g, int prec) {
-    return size_t(g.S) * 12 * (prec == WL_F64 ? 16 : 8);
+    // FP16 blocks end with one FP32 scale per site
+    return size_t(g.S) * (12 * complex_bytes(prec) + (prec == WL_F16S ? 4 : 0));
 }
 
 size_t gauge_bytes(const Geom &g, int prec, bool link12) {
-    return size_t(2) * 4 * (link12 ? 6 : 9) * (prec == WL_F64 ? 16 : 8) * size_t(g.S);
+    return size_t(2) * 4 * (link12 ? 6 : 9) * complex_bytes(prec) * size_t(g.S);
 }
 
 }  // namespace wl
@@ -64,7 +67,7 @@ constexpr uint32_t kKnownFlags = WL_PREC_MASK | WL_LINK12 | WL_DAG | WL_HOP | WL
 
 bool get_prec(uint32_t flags, int *prec, std::string *why) {
     const uint32_t p = flags & WL_PREC_MASK;
-    if (p != WL_F64 && p != WL_F32) {
+    if (p != WL_F64 && p != WL_F32 && p != WL_F16S) {
         *why = "unsupported precision flag";
         return false;
     }
@@ -268,8 +271,10 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
         return fail(WL_EINVAL, why);
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
-    if ((flags & WL_PREC_MASK) != WL_F64)
-        return fail(WL_EINVAL, "solver buffers are FP64 (use WL_MIXED for an FP32 inner solve)");
+    const uint32_t inner = flags & WL_PREC_MASK;
+    if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
+        return fail(WL_EINVAL, "solver buffers are FP64; a lower precision (WL_F32, WL_F16S) "
+                               "selects the inner solve of WL_MIXED");
     if (flags & (WL_DAG | WL_HOP)) return fail(WL_EINVAL, "WL_DAG / WL_HOP do not apply to solves");
     if (!gauge || !b || !x || !work) return fail(WL_EINVAL, "NULL buffer");
     if (b == x) return fail(WL_EINVAL, "b and x alias");

@@ -1,5 +1,5 @@
 // wl_blas.hip -- site-parallel vector kernels on packed spinor fields, and the
-// canonical <-> packed layout conversions.
+// canonical <-> packed layout and precision conversions.
 //
 // Every kernel maps one thread to one checkerboard site of one parity block,
 // so padding entries (index >= Vh) are never touched and reductions see only
@@ -15,18 +15,20 @@ namespace wl {
 struct BlasArgs {
     Geom g;
     int npar;
-    int nblocks;
+    int nblocks;          // nb_rhs * nrhs
+    int nb_rhs;           // blocks per right-hand side
+    int nrhs;
+    size_t fstride;       // bytes between the fields of consecutive RHS
     size_t blk;           // bytes between parity blocks of one field
     char *v[6];
     double a;
-    Scalars *sc;
+    Scalars *sc;          // RHS r reads sc[r]
     const int *skip;
     Reduce red;
 };
 
-template <typename R>
-__device__ __forceinline__ void *blk_ptr(const BlasArgs &a, int k, int par) {
-    return a.v[k] + par * a.blk;
+__device__ __forceinline__ void *blk_ptr(const BlasArgs &a, int k, int par, size_t fo) {
+    return a.v[k] + fo + par * a.blk;
 }
 
 template <typename R>
@@ -45,11 +47,21 @@ template <> struct OpSums<kOpBiXR> { static constexpr int value = 3; };
 template <> struct OpSums<kOpCopyNorm2> { static constexpr int value = 1; };
 template <> struct OpSums<kOpCopy2Norm2> { static constexpr int value = 1; };
 
-template <typename R, int OP>
+static bool op_reduces(int op) {
+    return op == kOpNorm2 || op == kOpXmy || op == kOpCgXR || op == kOpBiXR ||
+           op == kOpCopyNorm2 || op == kOpCopy2Norm2;
+}
+
+template <typename ST, int OP>
 __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
-    if (a.skip && *a.skip) return;
+    using R = Real<ST>;
     constexpr int NS = OpSums<OP>::value;
-    const int b = xcd_block(blockIdx.x, a.nblocks);
+    const int bl = xcd_block(blockIdx.x, a.nblocks);
+    const int rhs = bl % a.nrhs;
+    const int b = bl / a.nrhs;
+    if (rhs_skip(a.skip, rhs)) return;
+    const size_t fo = size_t(rhs) * a.fstride;
+    const Scalars *sc = a.sc ? a.sc + rhs : nullptr;
     const int par = b / a.g.bpp;
     const int i = (b - par * a.g.bpp) * kBlock + threadIdx.x;
     const int S = a.g.S;
@@ -59,85 +71,85 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
         if constexpr (OP == kOpZero) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = {R(0), R(0)};
-            store_spinor<R>(blk_ptr<R>(a, 0, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, y);
         } else if constexpr (OP == kOpCopy || OP == kOpCopyNorm2 || OP == kOpCopy2Norm2) {
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            store_spinor<R>(blk_ptr<R>(a, 1, par), S, i, x);
-            if constexpr (OP == kOpCopy2Norm2) store_spinor<R>(blk_ptr<R>(a, 2, par), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, x);
+            if constexpr (OP == kOpCopy2Norm2) store_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, x);
             if constexpr (NS > 0) sums[0] = norm2(x);
         } else if constexpr (OP == kOpNorm2) {
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
             sums[0] = norm2(x);
         } else if constexpr (OP == kOpXmy) {        // y = x - y
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = x[k] - y[k];
-            store_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
             sums[0] = norm2(y);
         } else if constexpr (OP == kOpAxpy) {       // y += a x
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
             const R s = R(a.a);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = y[k] + s * x[k];
-            store_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
         } else if constexpr (OP == kOpCgXR) {       // x += al p; r -= al q
-            const R al = R(a.sc->alpha);
+            const R al = R(sc->alpha);
             cpx<R> p[12], q[12];
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, p);
-            load_spinor<R>(blk_ptr<R>(a, 2, par), S, i, y);
-            load_spinor<R>(blk_ptr<R>(a, 3, par), S, i, q);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, p);
+            load_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, y);
+            load_spinor<ST>(blk_ptr(a, 3, par, fo), S, i, q);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = x[k] + al * p[k];
                 y[k] = y[k] - al * q[k];
             }
-            store_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            store_spinor<R>(blk_ptr<R>(a, 2, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            store_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, y);
             sums[0] = norm2(y);
         } else if constexpr (OP == kOpCgP) {        // p = r + be p
-            const R be = R(a.sc->beta);
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            const R be = R(sc->beta);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = x[k] + be * y[k];
-            store_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
         } else if constexpr (OP == kOpBiP) {        // p = r + be (p - om v)
-            const cpx<R> be{R(a.sc->beta_c[0]), R(a.sc->beta_c[1])};
-            const cpx<R> om{R(a.sc->omega[0]), R(a.sc->omega[1])};
+            const cpx<R> be{R(sc->beta_c[0]), R(sc->beta_c[1])};
+            const cpx<R> om{R(sc->omega[0]), R(sc->omega[1])};
             cpx<R> v[12];
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
-            load_spinor<R>(blk_ptr<R>(a, 2, par), S, i, v);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
+            load_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, v);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = x[k] + be * (y[k] - om * v[k]);
-            store_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
         } else if constexpr (OP == kOpBiS) {        // s = r - al v
-            const cpx<R> al{R(a.sc->alpha_c[0]), R(a.sc->alpha_c[1])};
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, y);
+            const cpx<R> al{R(sc->alpha_c[0]), R(sc->alpha_c[1])};
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) y[k] = x[k] - al * y[k];
-            store_spinor<R>(blk_ptr<R>(a, 2, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, y);
         } else if constexpr (OP == kOpBiXR) {       // x += al p + om s; r = s - om t
-            const cpx<R> al{R(a.sc->alpha_c[0]), R(a.sc->alpha_c[1])};
-            const cpx<R> om{R(a.sc->omega[0]), R(a.sc->omega[1])};
+            const cpx<R> al{R(sc->alpha_c[0]), R(sc->alpha_c[1])};
+            const cpx<R> om{R(sc->omega[0]), R(sc->omega[1])};
             cpx<R> p[12], s[12], t[12];
-            load_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            load_spinor<R>(blk_ptr<R>(a, 1, par), S, i, p);
-            load_spinor<R>(blk_ptr<R>(a, 2, par), S, i, s);
-            load_spinor<R>(blk_ptr<R>(a, 3, par), S, i, t);
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, p);
+            load_spinor<ST>(blk_ptr(a, 2, par, fo), S, i, s);
+            load_spinor<ST>(blk_ptr(a, 3, par, fo), S, i, t);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 x[k] = x[k] + al * p[k] + om * s[k];
                 y[k] = s[k] - om * t[k];
             }
-            store_spinor<R>(blk_ptr<R>(a, 0, par), S, i, x);
-            store_spinor<R>(blk_ptr<R>(a, 4, par), S, i, y);
+            store_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            store_spinor<ST>(blk_ptr(a, 4, par, fo), S, i, y);
             cpx<R> rh[12];
-            load_spinor<R>(blk_ptr<R>(a, 5, par), S, i, rh);
+            load_spinor<ST>(blk_ptr(a, 5, par, fo), S, i, rh);
             sums[0] = norm2(y);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {   // <rhat, r>
@@ -146,14 +158,66 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
             }
         }
     }
-    if constexpr (NS > 0) grid_reduce<NS>(sums, a.red, b, a.nblocks);
+    if constexpr (NS > 0)
+        block_partial<NS>(sums, rhs_reduce(a.red, rhs, a.nb_rhs).partials, b, a.nb_rhs);
 }
 
-template <typename R>
-static hipError_t blas_prec(const BlasArgs &a, int op, hipStream_t s) {
+// One block per right-hand side: add the nb partials of each sum in a fixed
+// order (thread-strided, then the shuffle tree, then the waves in order),
+// store the totals and run the solver epilogue.
+template <int NS>
+__global__ void __launch_bounds__(kBlock) finish_kernel(Reduce red, int nb, const int *skip) {
+    const int r = blockIdx.x;
+    if (rhs_skip(skip, r)) return;
+    const Reduce rr = rhs_reduce(red, r, nb);
+    double acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] += rr.partials[s * nb + b];
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh[kWaves][NS];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] += __shfl_xor(acc[s], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) sh[wave][s] = acc[s];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[kMaxSums] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += sh[w][s];
+            tot[s] = t;
+            rr.result[s] = t;
+        }
+        if (rr.sc) run_epilogue(rr.epilogue, tot, rr.sc);
+    }
+}
+
+hipError_t launch_finish(const Reduce &red, int ns, int nb, int nrhs, const int *skip,
+                         hipStream_t s) {
+    const dim3 grid(nrhs), block(kBlock);
+    switch (ns) {
+    case 1: hipLaunchKernelGGL((finish_kernel<1>), grid, block, 0, s, red, nb, skip); break;
+    case 2: hipLaunchKernelGGL((finish_kernel<2>), grid, block, 0, s, red, nb, skip); break;
+    case 3: hipLaunchKernelGGL((finish_kernel<3>), grid, block, 0, s, red, nb, skip); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename ST>
+static hipError_t blas_storage(const BlasArgs &a, int op, hipStream_t s) {
     const dim3 grid(a.nblocks), block(kBlock);
 #define WL_CASE(OPV) \
-    case OPV: hipLaunchKernelGGL((blas_kernel<R, OPV>), grid, block, 0, s, a); break;
+    case OPV: hipLaunchKernelGGL((blas_kernel<ST, OPV>), grid, block, 0, s, a); break;
     switch (op) {
         WL_CASE(kOpZero)
         WL_CASE(kOpCopy)
@@ -174,22 +238,27 @@ static hipError_t blas_prec(const BlasArgs &a, int op, hipStream_t s) {
 }
 
 hipError_t launch_blas(const Geom &g, int prec, const BlasCall &call, hipStream_t s) {
-    const bool reduces = call.op == kOpNorm2 || call.op == kOpXmy || call.op == kOpCgXR ||
-                         call.op == kOpBiXR || call.op == kOpCopyNorm2 || call.op == kOpCopy2Norm2;
-    if (reduces && (!call.red || !call.red->partials || !call.red->counter || !call.red->result))
+    if (op_reduces(call.op) &&
+        (!call.red || !call.red->partials || (!call.red->result && !call.red->sc)))
         return hipErrorInvalidValue;
     BlasArgs a;
     a.g = g;
     a.npar = call.npar;
-    a.nblocks = g.bpp * call.npar;
+    a.nrhs = call.nrhs < 1 ? 1 : call.nrhs;
+    a.nb_rhs = g.bpp * call.npar;
+    a.nblocks = a.nb_rhs * a.nrhs;
+    a.fstride = call.fstride;
     a.blk = spinor_block_bytes(g, prec);
     for (int k = 0; k < 6; ++k) a.v[k] = static_cast<char *>(call.v[k]);
     a.a = call.a;
     a.sc = call.sc;
     a.skip = call.skip;
     if (call.red) a.red = *call.red;
-    else a.red = Reduce{nullptr, nullptr, nullptr, kEpiNone, nullptr};
-    return prec == WL_F64 ? blas_prec<double>(a, call.op, s) : blas_prec<float>(a, call.op, s);
+    else a.red = Reduce{nullptr, nullptr, kEpiNone, nullptr};
+    const hipError_t e =
+        with_storage(prec, [&](auto tag) { return blas_storage<decltype(tag)>(a, call.op, s); });
+    if (e != hipSuccess || !op_reduces(call.op)) return e;
+    return launch_finish(a.red, call.op == kOpBiXR ? 3 : 1, a.nb_rhs, a.nrhs, a.skip, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,9 +279,10 @@ __device__ __forceinline__ SiteMap site_map(const Geom &g, int s) {
     return {(x + y + z + t) & 1, s >> 1};
 }
 
-template <typename R, int NCL>
+template <typename ST, int NCL>
 __global__ void __launch_bounds__(kBlock) pack_gauge_kernel(Geom g, const double2 *canon,
                                                             void *packed) {
+    using R = Real<ST>;
     const int gid = blockIdx.x * kBlock + threadIdx.x;   // = 4 s + mu
     if (gid >= 8 * g.Vh) return;
     const int s = gid >> 2, mu = gid & 3;
@@ -223,14 +293,13 @@ __global__ void __launch_bounds__(kBlock) pack_gauge_kernel(Geom g, const double
         const double2 c = canon[gid * 9 + k];
         u[k] = {R(c.x), R(c.y)};
     }
-    using F = LinkFmt<R, NCL>;
-    typename F::T *base = static_cast<typename F::T *>(packed) + (m.par * 4 + mu) * F::NCH * g.S;
-    store_cplx<R, NCL, F::CW>(base, g.S, m.cb, u);
+    store_link_raw<ST, NCL>(packed, g.S, m.par, mu, m.cb, u);
 }
 
-template <typename R>
+template <typename ST>
 __global__ void __launch_bounds__(kBlock) pack_spinor_kernel(Geom g, const double2 *canon,
                                                              void *packed, size_t blk) {
+    using R = Real<ST>;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= 2 * g.Vh) return;
     const SiteMap m = site_map(g, s);
@@ -240,22 +309,23 @@ __global__ void __launch_bounds__(kBlock) pack_spinor_kernel(Geom g, const doubl
         const double2 c = canon[s * 12 + k];
         v[k] = {R(c.x), R(c.y)};
     }
-    store_spinor<R>(static_cast<char *>(packed) + m.par * blk, g.S, m.cb, v);
+    store_spinor<ST>(static_cast<char *>(packed) + m.par * blk, g.S, m.cb, v);
 }
 
-template <typename R>
+template <typename ST>
 __global__ void __launch_bounds__(kBlock) unpack_spinor_kernel(Geom g, const void *packed,
                                                                double2 *canon, size_t blk) {
+    using R = Real<ST>;
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= 2 * g.Vh) return;
     const SiteMap m = site_map(g, s);
     cpx<R> v[12];
-    load_spinor<R>(static_cast<const char *>(packed) + m.par * blk, g.S, m.cb, v);
+    load_spinor<ST>(static_cast<const char *>(packed) + m.par * blk, g.S, m.cb, v);
 #pragma unroll
     for (int k = 0; k < 12; ++k) canon[s * 12 + k] = double2{double(v[k].re), double(v[k].im)};
 }
 
-template <typename RS, typename RD>
+template <typename SS, typename SD>
 __global__ void __launch_bounds__(kBlock) convert_spinor_kernel(Geom g, const char *src,
                                                                 size_t sblk, char *dst,
                                                                 size_t dblk) {
@@ -263,46 +333,43 @@ __global__ void __launch_bounds__(kBlock) convert_spinor_kernel(Geom g, const ch
     const int par = b / g.bpp;
     const int i = (b - par * g.bpp) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    cpx<RS> v[12];
-    cpx<RD> w[12];
-    load_spinor<RS>(src + par * sblk, g.S, i, v);
+    cpx<Real<SS>> v[12];
+    cpx<Real<SD>> w[12];
+    load_spinor<SS>(src + par * sblk, g.S, i, v);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = {RD(v[k].re), RD(v[k].im)};
-    store_spinor<RD>(dst + par * dblk, g.S, i, w);
+    for (int k = 0; k < 12; ++k) w[k] = {Real<SD>(v[k].re), Real<SD>(v[k].im)};
+    store_spinor<SD>(dst + par * dblk, g.S, i, w);
 }
 
-__global__ void __launch_bounds__(kBlock) accum_f32_kernel(Geom g, const char *x32, size_t sblk,
-                                                           char *y64, size_t dblk) {
+template <typename SS>
+__global__ void __launch_bounds__(kBlock) accum_lo_kernel(Geom g, const char *x, size_t sblk,
+                                                          char *y64, size_t dblk) {
     const int b = blockIdx.x;
     const int par = b / g.bpp;
     const int i = (b - par * g.bpp) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    cpx<float> v[12];
+    cpx<Real<SS>> v[12];
     cpx<double> w[12];
-    load_spinor<float>(x32 + par * sblk, g.S, i, v);
+    load_spinor<SS>(x + par * sblk, g.S, i, v);
     load_spinor<double>(y64 + par * dblk, g.S, i, w);
 #pragma unroll
     for (int k = 0; k < 12; ++k) w[k] = {w[k].re + double(v[k].re), w[k].im + double(v[k].im)};
     store_spinor<double>(y64 + par * dblk, g.S, i, w);
 }
 
-template <int NCL>
+template <typename SD, int NCL>
 __global__ void __launch_bounds__(kBlock) convert_gauge_kernel(Geom g, const void *src64,
-                                                               void *dst32) {
+                                                               void *dst) {
     const int b = blockIdx.x;                 // 8 * bpp blocks: (par, mu) major
     const int pm = b / g.bpp;
     const int i = (b - pm * g.bpp) * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
-    using F64 = LinkFmt<double, NCL>;
-    using F32 = LinkFmt<float, NCL>;
     cpx<double> u[NCL];
-    cpx<float> w[NCL];
-    load_cplx<double, NCL, F64::CW>(static_cast<const typename F64::T *>(src64) + pm * F64::NCH * g.S,
-                                    g.S, i, u);
+    cpx<Real<SD>> w[NCL];
+    load_link_raw<double, NCL>(src64, g.S, pm >> 2, pm & 3, i, u);
 #pragma unroll
-    for (int k = 0; k < NCL; ++k) w[k] = {float(u[k].re), float(u[k].im)};
-    store_cplx<float, NCL, F32::CW>(static_cast<typename F32::T *>(dst32) + pm * F32::NCH * g.S,
-                                    g.S, i, w);
+    for (int k = 0; k < NCL; ++k) w[k] = {Real<SD>(u[k].re), Real<SD>(u[k].im)};
+    store_link_raw<SD, NCL>(dst, g.S, pm >> 2, pm & 3, i, w);
 }
 
 static int cdiv(long a, long b) { return int((a + b - 1) / b); }
@@ -311,13 +378,12 @@ hipError_t launch_pack_gauge(const Geom &g, int prec, bool link12, const void *c
                              void *packed, hipStream_t s) {
     const dim3 grid(cdiv(8L * g.Vh, kBlock)), block(kBlock);
     const double2 *c = static_cast<const double2 *>(canon);
-    if (prec == WL_F64) {
-        if (link12) hipLaunchKernelGGL((pack_gauge_kernel<double, 6>), grid, block, 0, s, g, c, packed);
-        else hipLaunchKernelGGL((pack_gauge_kernel<double, 9>), grid, block, 0, s, g, c, packed);
-    } else {
-        if (link12) hipLaunchKernelGGL((pack_gauge_kernel<float, 6>), grid, block, 0, s, g, c, packed);
-        else hipLaunchKernelGGL((pack_gauge_kernel<float, 9>), grid, block, 0, s, g, c, packed);
-    }
+    with_storage(prec, [&](auto tag) {
+        using ST = decltype(tag);
+        if (link12) hipLaunchKernelGGL((pack_gauge_kernel<ST, 6>), grid, block, 0, s, g, c, packed);
+        else hipLaunchKernelGGL((pack_gauge_kernel<ST, 9>), grid, block, 0, s, g, c, packed);
+        return 0;
+    });
     return hipGetLastError();
 }
 
@@ -326,8 +392,11 @@ hipError_t launch_pack_spinor(const Geom &g, int prec, const void *canon, void *
     const dim3 grid(cdiv(2L * g.Vh, kBlock)), block(kBlock);
     const double2 *c = static_cast<const double2 *>(canon);
     const size_t blk = spinor_block_bytes(g, prec);
-    if (prec == WL_F64) hipLaunchKernelGGL((pack_spinor_kernel<double>), grid, block, 0, s, g, c, packed, blk);
-    else hipLaunchKernelGGL((pack_spinor_kernel<float>), grid, block, 0, s, g, c, packed, blk);
+    with_storage(prec, [&](auto tag) {
+        hipLaunchKernelGGL((pack_spinor_kernel<decltype(tag)>), grid, block, 0, s, g, c, packed,
+                           blk);
+        return 0;
+    });
     return hipGetLastError();
 }
 
@@ -336,8 +405,11 @@ hipError_t launch_unpack_spinor(const Geom &g, int prec, const void *packed, voi
     const dim3 grid(cdiv(2L * g.Vh, kBlock)), block(kBlock);
     double2 *c = static_cast<double2 *>(canon);
     const size_t blk = spinor_block_bytes(g, prec);
-    if (prec == WL_F64) hipLaunchKernelGGL((unpack_spinor_kernel<double>), grid, block, 0, s, g, packed, c, blk);
-    else hipLaunchKernelGGL((unpack_spinor_kernel<float>), grid, block, 0, s, g, packed, c, blk);
+    with_storage(prec, [&](auto tag) {
+        hipLaunchKernelGGL((unpack_spinor_kernel<decltype(tag)>), grid, block, 0, s, g, packed, c,
+                           blk);
+        return 0;
+    });
     return hipGetLastError();
 }
 
@@ -347,30 +419,38 @@ hipError_t launch_convert_spinor(const Geom &g, int npar, int src_prec, const vo
     const char *sp = static_cast<const char *>(src);
     char *dp = static_cast<char *>(dst);
     const size_t sb = spinor_block_bytes(g, src_prec), db = spinor_block_bytes(g, dst_prec);
-    if (src_prec == WL_F64 && dst_prec == WL_F32)
-        hipLaunchKernelGGL((convert_spinor_kernel<double, float>), grid, block, 0, s, g, sp, sb, dp, db);
-    else if (src_prec == WL_F32 && dst_prec == WL_F64)
-        hipLaunchKernelGGL((convert_spinor_kernel<float, double>), grid, block, 0, s, g, sp, sb, dp, db);
-    else if (src_prec == WL_F64)
-        hipLaunchKernelGGL((convert_spinor_kernel<double, double>), grid, block, 0, s, g, sp, sb, dp, db);
-    else
-        hipLaunchKernelGGL((convert_spinor_kernel<float, float>), grid, block, 0, s, g, sp, sb, dp, db);
+    with_storage(src_prec, [&](auto stag) {
+        return with_storage(dst_prec, [&](auto dtag) {
+            hipLaunchKernelGGL((convert_spinor_kernel<decltype(stag), decltype(dtag)>), grid, block,
+                               0, s, g, sp, sb, dp, db);
+            return 0;
+        });
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_accum_f32(const Geom &g, int npar, const void *x32, void *y64, hipStream_t s) {
+hipError_t launch_accum_lo(const Geom &g, int npar, int src_prec, const void *x, void *y64,
+                           hipStream_t s) {
     const dim3 grid(g.bpp * npar), block(kBlock);
-    hipLaunchKernelGGL(accum_f32_kernel, grid, block, 0, s, g, static_cast<const char *>(x32),
-                       spinor_block_bytes(g, WL_F32), static_cast<char *>(y64),
-                       spinor_block_bytes(g, WL_F64));
+    const char *xp = static_cast<const char *>(x);
+    char *yp = static_cast<char *>(y64);
+    const size_t sb = spinor_block_bytes(g, src_prec), db = spinor_block_bytes(g, WL_F64);
+    with_storage(src_prec, [&](auto tag) {
+        hipLaunchKernelGGL((accum_lo_kernel<decltype(tag)>), grid, block, 0, s, g, xp, sb, yp, db);
+        return 0;
+    });
     return hipGetLastError();
 }
 
-hipError_t launch_convert_gauge(const Geom &g, bool link12, const void *src64, void *dst32,
-                                hipStream_t s) {
+hipError_t launch_convert_gauge(const Geom &g, bool link12, const void *src64, int dst_prec,
+                                void *dst, hipStream_t s) {
     const dim3 grid(g.bpp * 8), block(kBlock);
-    if (link12) hipLaunchKernelGGL((convert_gauge_kernel<6>), grid, block, 0, s, g, src64, dst32);
-    else hipLaunchKernelGGL((convert_gauge_kernel<9>), grid, block, 0, s, g, src64, dst32);
+    with_storage(dst_prec, [&](auto tag) {
+        using SD = decltype(tag);
+        if (link12) hipLaunchKernelGGL((convert_gauge_kernel<SD, 6>), grid, block, 0, s, g, src64, dst);
+        else hipLaunchKernelGGL((convert_gauge_kernel<SD, 9>), grid, block, 0, s, g, src64, dst);
+        return 0;
+    });
     return hipGetLastError();
 }
 
@@ -385,6 +465,15 @@ __global__ void set_target_kernel(Scalars *sc, double target) {
 
 hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s) {
     hipLaunchKernelGGL(set_target_kernel, dim3(1), dim3(64), 0, s, sc, target);
+    return hipGetLastError();
+}
+
+__global__ void beta_ratio_kernel(Scalars *sc, double rr_old) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->beta = sc->rr / rr_old;
+}
+
+hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s) {
+    hipLaunchKernelGGL(beta_ratio_kernel, dim3(1), dim3(64), 0, s, sc, rr_old);
     return hipGetLastError();
 }
 

@@ -1,8 +1,8 @@
 // wl_internal.h -- shared declarations of libwilson.so (not installed).
 //
 // Geometry of the even-odd ("WL") layout, the complex type used in kernels,
-// vector-chunk loads and stores, the solver scalar block, and the launchers
-// each .hip file provides to the host-side drivers.
+// storage access for the three storage precisions, the solver scalar block,
+// and the launchers each .hip file provides to the host-side drivers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,7 +16,10 @@
 
 namespace wl {
 
-constexpr int kBlock = 256;      // threads per block of every site kernel
+#ifndef WL_BLOCK
+#define WL_BLOCK 256
+#endif
+constexpr int kBlock = WL_BLOCK; // threads per block of every site kernel (multiple of 64)
 constexpr int kMaxSums = 4;      // doubles per fused reduction
 
 // ---------------------------------------------------------------------------
@@ -62,96 +65,164 @@ template <typename R>
 __device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.re, -a.im}; }
 
 // ---------------------------------------------------------------------------
-// Storage chunks: a field of NC complex numbers per site is stored as NC/CW
-// arrays of vectors holding CW complex numbers each, one array per chunk,
-// each of length S (sites of one parity).
+// Storage precisions. ST is the storage type of a field: double, float, or
+// Half (IEEE binary16; spinors carry one FP32 scale per site). Arithmetic runs
+// in Real<ST>: FP64 for double storage, FP32 otherwise.
+//
+// A field of NC complex numbers per site is stored as NC/CW arrays ("chunks")
+// of vectors of CW complex numbers, each array S sites long, so a wave's 64
+// lanes read 64 consecutive sites of one chunk.
 // ---------------------------------------------------------------------------
-template <typename R, int CW> struct Vec;
-template <> struct Vec<double, 1> { using T = double2; };
-template <> struct Vec<float, 1> { using T = float2; };
-template <> struct Vec<float, 2> { using T = float4; };
+struct Half {};
 
-template <typename R>
-struct SpinorFmt {
-    static constexpr int CW = std::is_same<R, double>::value ? 1 : 2;
-    static constexpr int NCH = 12 / CW;   // chunks per site
-    using T = typename Vec<R, CW>::T;
-};
+template <typename ST>
+using Real = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
 
-template <typename R, int NCL>   // NCL = 9 (18-real) or 6 (12-real)
-struct LinkFmt {
-    static constexpr int CW = (std::is_same<R, double>::value || NCL == 9) ? 1 : 2;
-    static constexpr int NCH = NCL / CW;
-    using T = typename Vec<R, CW>::T;
-};
+template <typename ST>
+constexpr int prec_of() {
+    return std::is_same<ST, double>::value ? WL_F64 : std::is_same<ST, float>::value ? WL_F32
+                                                                                      : WL_F16S;
+}
 
-template <typename R, int NC, int CW>
-__device__ __forceinline__ void load_cplx(const typename Vec<R, CW>::T *__restrict__ p,
-                                          int S, int i, cpx<R> *v) {
+// bytes of one stored complex number
+template <typename ST>
+constexpr int cbytes() {
+    return std::is_same<ST, double>::value ? 16 : std::is_same<ST, float>::value ? 8 : 4;
+}
+
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+template <typename ST, int CW> struct Vec;
+template <> struct Vec<double, 1> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct Vec<float, 1> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct Vec<float, 2> { typedef float T __attribute__((ext_vector_type(4))); };
+template <> struct Vec<Half, 1> { typedef h2v T; };
+template <> struct Vec<Half, 2> { typedef h4v T; };
+template <> struct Vec<Half, 4> { typedef h8v T; };
+
+// complex numbers per chunk: 16-byte chunks for spinors where possible
+template <typename ST> constexpr int spinor_cw() { return 16 / cbytes<ST>(); }
+// links: two complex per chunk for 12-real FP32/FP16 storage, else one (9 is odd)
+template <typename ST, int NCL> constexpr int link_cw() {
+    return (std::is_same<ST, double>::value || NCL == 9) ? 1 : 2;
+}
+
+template <typename ST, int NC, int CW>
+__device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Real<ST>> *v) {
+    using T = typename Vec<ST, CW>::T;
+    using R = Real<ST>;
+    const T *p = static_cast<const T *>(base);
 #pragma unroll
     for (int j = 0; j < NC / CW; ++j) {
-        const typename Vec<R, CW>::T c = p[j * S + i];
-        if constexpr (CW == 1) {
-            v[j].re = c.x;
-            v[j].im = c.y;
-        } else {
-            v[2 * j].re = c.x;
-            v[2 * j].im = c.y;
-            v[2 * j + 1].re = c.z;
-            v[2 * j + 1].im = c.w;
+        const T c = p[j * S + i];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            v[CW * j + k].re = R(c[2 * k]);
+            v[CW * j + k].im = R(c[2 * k + 1]);
         }
     }
 }
 
-template <typename R, int NC, int CW>
-__device__ __forceinline__ void store_cplx(typename Vec<R, CW>::T *__restrict__ p,
-                                           int S, int i, const cpx<R> *v) {
+template <typename ST> struct Elem { using T = ST; };
+template <> struct Elem<Half> { using T = _Float16; };
+
+template <typename ST, int NC, int CW, bool NT = false>
+__device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<Real<ST>> *v,
+                                           Real<ST> scale = Real<ST>(1)) {
+    using T = typename Vec<ST, CW>::T;
+    using E = typename Elem<ST>::T;
+    T *p = static_cast<T *>(base);
 #pragma unroll
     for (int j = 0; j < NC / CW; ++j) {
-        typename Vec<R, CW>::T c;
-        if constexpr (CW == 1) {
-            c.x = v[j].re;
-            c.y = v[j].im;
-        } else {
-            c.x = v[2 * j].re;
-            c.y = v[2 * j].im;
-            c.z = v[2 * j + 1].re;
-            c.w = v[2 * j + 1].im;
+        T c;
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            c[2 * k] = static_cast<E>(v[CW * j + k].re * scale);
+            c[2 * k + 1] = static_cast<E>(v[CW * j + k].im * scale);
         }
-        p[j * S + i] = c;
+        if constexpr (NT) __builtin_nontemporal_store(c, &p[j * S + i]);
+        else p[j * S + i] = c;
     }
 }
 
-// one site of a spinor parity block
-template <typename R>
-__device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<R> v[12]) {
-    using F = SpinorFmt<R>;
-    load_cplx<R, 12, F::CW>(static_cast<const typename F::T *>(blk), S, i, v);
+// ---- spinors: one site of one parity block --------------------------------
+// Half blocks hold the 24 binary16 values of psi/s (s = max |component| of the
+// site, so every stored value lies in [-1, 1]) followed by the S scales.
+template <typename ST>
+__device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<Real<ST>> v[12]) {
+    load_cplx<ST, 12, spinor_cw<ST>()>(blk, S, i, v);
+    if constexpr (std::is_same<ST, Half>::value) {
+        const float s = reinterpret_cast<const float *>(static_cast<const char *>(blk) +
+                                                        size_t(S) * 48)[i];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = s * v[k];
+    }
 }
-template <typename R>
-__device__ __forceinline__ void store_spinor(void *blk, int S, int i, const cpx<R> v[12]) {
-    using F = SpinorFmt<R>;
-    store_cplx<R, 12, F::CW>(static_cast<typename F::T *>(blk), S, i, v);
+
+template <typename ST, bool NT = false>
+__device__ __forceinline__ void store_spinor(void *blk, int S, int i, const cpx<Real<ST>> v[12]) {
+    if constexpr (std::is_same<ST, Half>::value) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float s = m > 0.f ? m : 1.f;
+        store_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v, 1.f / s);
+        reinterpret_cast<float *>(static_cast<char *>(blk) + size_t(S) * 48)[i] = s;
+    } else {
+        store_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v);
+    }
+}
+
+// ---- links: U_mu at checkerboard index i of parity par --------------------
+template <typename ST, int NCL>
+__device__ __forceinline__ const void *link_block(const void *gauge, int S, int par, int mu) {
+    return static_cast<const char *>(gauge) + size_t(par * 4 + mu) * NCL * cbytes<ST>() * S;
+}
+
+template <typename ST, int NCL>
+__device__ __forceinline__ void load_link_raw(const void *gauge, int S, int par, int mu, int i,
+                                              cpx<Real<ST>> *u) {
+    load_cplx<ST, NCL, link_cw<ST, NCL>()>(link_block<ST, NCL>(gauge, S, par, mu), S, i, u);
+}
+
+template <typename ST, int NCL>
+__device__ __forceinline__ void store_link_raw(void *gauge, int S, int par, int mu, int i,
+                                               const cpx<Real<ST>> *u) {
+    store_cplx<ST, NCL, link_cw<ST, NCL>()>(
+        const_cast<void *>(link_block<ST, NCL>(gauge, S, par, mu)), S, i, u);
 }
 
 // Byte sizes
 size_t spinor_block_bytes(const Geom &g, int prec);   // one parity block
 size_t gauge_bytes(const Geom &g, int prec, bool link12);
 
+// Host-side dispatch from a WL_* precision to a storage type tag.
+template <typename F>
+auto with_storage(int prec, F &&f) {
+    if (prec == WL_F64) return f(double{});
+    if (prec == WL_F32) return f(float{});
+    return f(Half{});
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic fused reductions
 // ---------------------------------------------------------------------------
 // Every reducing kernel writes one partial per block per sum into `partials`
-// ([sum][block]); the last block to finish (counted on `counter`) adds the
-// partials in a fixed order, writes the totals, runs the epilogue, and resets
-// the counter to zero. The totals therefore do not depend on block timing.
+// ([rhs][sum][block]); a finish kernel (one block per RHS) adds the partials
+// in a fixed order, writes the totals and runs the epilogue. The totals do not
+// depend on block timing.
 struct Reduce {
-    double *partials;     // kMaxSums * max_blocks doubles
-    unsigned *counter;    // zero between launches
-    double *result;       // kMaxSums doubles (may alias scalars)
+    double *partials;     // nrhs * kMaxSums * blocks-per-RHS doubles
+    double *result;       // kMaxSums doubles per RHS (unused when sc is set)
     int epilogue;         // Epi::*
-    struct Scalars *sc;   // solver state the epilogue updates
+    struct Scalars *sc;   // solver state the epilogue updates (RHS r: sc[r])
 };
+
+// Add up the partials of a reducing launch (ns sums, nb blocks per RHS).
+hipError_t launch_finish(const Reduce &red, int ns, int nb, int nrhs, const int *skip,
+                         hipStream_t s);
 
 enum Epi : int {
     kEpiNone = 0,
@@ -190,7 +261,7 @@ struct Phases {
 };
 
 // out[p] = (xs ? xs[p] : 0) + c * D_{p,1-p} in[1-p] for the output parities
-// p in {first_par, ...} (npar = 1 or 2). Optional fused ||out||^2 reduction.
+// p in {first_par, ...} (npar = 1 or 2). Optional fused reduction.
 struct HopCall {
     const void *gauge;
     const void *in[2];
@@ -203,6 +274,8 @@ struct HopCall {
     bool dag;
     const int *skip;      // kernel is a no-op when *skip != 0 (may be null)
     const Reduce *red;    // null: no reduction
+    int nrhs = 1;         // fields of a batch, fstride bytes apart (gauge shared)
+    size_t fstride = 0;
 };
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s);
@@ -214,11 +287,11 @@ hipError_t launch_pack_spinor(const Geom &g, int prec, const void *canon, void *
                               hipStream_t s);
 hipError_t launch_unpack_spinor(const Geom &g, int prec, const void *packed, void *canon,
                                 hipStream_t s);
-// Packed FP64 <-> FP32 conversions (npar parity blocks of spinors; gauge)
+// Packed spinor precision conversion (npar parity blocks); FP64 gauge -> lower
 hipError_t launch_convert_spinor(const Geom &g, int npar, int src_prec, const void *src,
                                  int dst_prec, void *dst, hipStream_t s);
-hipError_t launch_convert_gauge(const Geom &g, bool link12, const void *src64, void *dst32,
-                                hipStream_t s);
+hipError_t launch_convert_gauge(const Geom &g, bool link12, const void *src64, int dst_prec,
+                                void *dst, hipStream_t s);
 
 // ---- BLAS-1 on packed spinor fields of npar parity blocks ----------------
 enum BlasOp : int {
@@ -240,18 +313,22 @@ struct BlasCall {
     int npar;
     void *v[6];           // operand parity-0 blocks, meaning per op
     double a;             // host scalar for kOpAxpy
-    Scalars *sc;
+    Scalars *sc;          // RHS r reads sc[r]
     const int *skip;
     const Reduce *red;
+    int nrhs = 1;         // fields of a batch, fstride bytes apart
+    size_t fstride = 0;
 };
 hipError_t launch_blas(const Geom &g, int prec, const BlasCall &call, hipStream_t s);
 
-// Convert an FP32 half or full field and accumulate into FP64: y64 += x32
-hipError_t launch_accum_f32(const Geom &g, int npar, const void *x32, void *y64,
-                            hipStream_t s);
+// y64 += x (x in FP32 or FP16 storage), npar parity blocks
+hipError_t launch_accum_lo(const Geom &g, int npar, int src_prec, const void *x, void *y64,
+                           hipStream_t s);
 
 // Initialise a Krylov loop's scalars: target, done = 0, status = WL_OK, iter = 0
 hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s);
+// CG direction update after a residual replacement: beta = sc->rr / rr_old
+hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s);
 
 // ---- solvers ---------------------------------------------------------------
 size_t workspace_bytes(const Geom &g, uint32_t flags);

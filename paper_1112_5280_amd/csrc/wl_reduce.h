@@ -1,4 +1,10 @@
-// wl_reduce.h -- block reduction, last-block finish and solver epilogues.
+// wl_reduce.h -- deterministic reductions, solver epilogues, block order.
+//
+// A reducing kernel leaves one partial sum per block and per summed quantity
+// (block_partial); a one-block-per-RHS finish kernel then adds the partials in
+// a fixed order, stores the totals and runs the solver epilogue
+// (finish_reduce). No atomics are involved, so the totals are bitwise
+// reproducible and nothing has to be reset between launches.
 #pragma once
 
 #include "wl_internal.h"
@@ -8,7 +14,7 @@ namespace wl {
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Updates of the solver scalars once the totals of a fused reduction are known.
-// Runs on one thread of the last block to finish.
+// Runs on one thread of the finish kernel.
 __device__ inline void run_epilogue(int epi, const double *tot, Scalars *sc) {
     switch (epi) {
     case kEpiCgInit: {
@@ -138,14 +144,14 @@ __device__ inline void run_epilogue(int epi, const double *tot, Scalars *sc) {
     }
 }
 
-// Sum NS per-thread values over the grid, deterministically; see Reduce.
-// Must be reached by every thread of every block of the launch.
+// Sum NS per-thread values over the block (wave64 shuffle tree, then the
+// waves in order) and store the block's totals at partials[s * nb + slot].
+// Must be reached by every thread of the block.
 template <int NS>
-__device__ __forceinline__ void grid_reduce(double (&v)[NS], const Reduce &red, int slot,
-                                            int nblocks) {
+__device__ __forceinline__ void block_partial(double (&v)[NS], double *partials, int slot,
+                                              int nb) {
     constexpr int kWaves = kBlock / 64;
     __shared__ double sh[kWaves][NS];
-    __shared__ int am_last;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -161,44 +167,8 @@ __device__ __forceinline__ void grid_reduce(double (&v)[NS], const Reduce &red, 
             double t = 0.0;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) t += sh[w][s];
-            red.partials[s * nblocks + slot] = t;
+            partials[s * nb + slot] = t;
         }
-        __threadfence();
-        const unsigned prev = atomicAdd(red.counter, 1u);
-        am_last = (prev == (unsigned)(nblocks - 1));
-    }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
-    double acc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock)
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-            acc[s] += __builtin_nontemporal_load(&red.partials[s * nblocks + b]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) acc[s] += __shfl_xor(acc[s], off, 64);
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) sh[wave][s] = acc[s];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot[kMaxSums] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) t += sh[w][s];
-            tot[s] = t;
-            red.result[s] = t;
-        }
-        if (red.sc) run_epilogue(red.epilogue, tot, red.sc);
-        __threadfence();
-        atomicExch(red.counter, 0u);
     }
 }
 
@@ -208,6 +178,26 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
     const int q = n >> 3, r = n & 7;
     const int k = b & 7, j = b >> 3;
     return k * q + (k < r ? k : r) + j;
+}
+
+// Batches of right-hand sides: RHS r owns the r-th Scalars entry and its own
+// nb partial slots per summed quantity.
+__device__ __forceinline__ Reduce rhs_reduce(const Reduce &red, int r, int nb) {
+    Reduce o = red;
+    o.partials = red.partials + size_t(r) * kMaxSums * nb;
+    if (red.sc) {
+        o.sc = red.sc + r;
+        o.result = o.sc->sums;
+    } else {
+        o.result = red.result + r * kMaxSums;
+    }
+    return o;
+}
+
+// `skip` points at the `done` flag of RHS 0; RHS r's flag is one Scalars further
+__device__ __forceinline__ bool rhs_skip(const int *skip, int r) {
+    return skip && *reinterpret_cast<const int *>(reinterpret_cast<const char *>(skip) +
+                                                  size_t(r) * sizeof(Scalars));
 }
 
 }  // namespace wl

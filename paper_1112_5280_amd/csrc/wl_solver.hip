@@ -6,9 +6,11 @@
 //   BiCGStab  van der Vorst's BiCGStab on M.
 //   WL_EO     both run on the Schur system Mhat_e x_e = b_e + kappa D_eo b_o,
 //             Mhat_e = 1 - kappa^2 D_eo D_oe, then x_o = b_o + kappa D_oe x_e.
-//   WL_MIXED  FP64 defect correction: r = b - M x in FP64, an FP32 Krylov solve
-//             of M e = r to a relative 1e-5, x += e in FP64, until the FP64
-//             true residual meets tol.
+//   WL_MIXED  Krylov iterations in FP32 or FP16 storage. CG keeps one Krylov
+//             sequence with reliable updates: whenever the low-precision
+//             residual has dropped by delta, x += x_lo in FP64 and the residual
+//             is recomputed in FP64 and copied back. BiCGStab uses FP64 defect
+//             correction: an inner solve of M e = r, then x += e.
 //
 // Every solve finishes with the FP64 true residual ||b - M x|| / ||b|| on the
 // full lattice; when it misses tol the Krylov loop restarts from x with a
@@ -32,9 +34,13 @@ constexpr size_t kAlign = 256;
 
 static size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// storage precision of the inner (low-precision) Krylov vectors of WL_MIXED
+static int lo_prec(uint32_t flags) {
+    return (flags & WL_PREC_MASK) == WL_F16S ? WL_F16S : WL_F32;
+}
+
 struct Workspace {
     Scalars *sc;
-    unsigned *counter;
     double *partials;
     char *v64[kVec64];
     void *gauge32;
@@ -48,8 +54,8 @@ static size_t header_bytes(const Geom &g) {
 size_t workspace_bytes(const Geom &g, uint32_t flags) {
     size_t n = header_bytes(g) + kVec64 * align_up(2 * spinor_block_bytes(g, WL_F64));
     if (flags & WL_MIXED)
-        n += align_up(gauge_bytes(g, WL_F32, flags & WL_LINK12)) +
-             kVec32 * align_up(2 * spinor_block_bytes(g, WL_F32));
+        n += align_up(gauge_bytes(g, lo_prec(flags), flags & WL_LINK12)) +
+             kVec32 * align_up(2 * spinor_block_bytes(g, lo_prec(flags)));
     return n;
 }
 
@@ -57,15 +63,14 @@ static Workspace carve(const Geom &g, uint32_t flags, void *work) {
     Workspace ws{};
     char *p = static_cast<char *>(work);
     ws.sc = reinterpret_cast<Scalars *>(p);
-    ws.counter = reinterpret_cast<unsigned *>(p + 1024);
     ws.partials = reinterpret_cast<double *>(p + 4096);
     p += header_bytes(g);
     const size_t f64 = align_up(2 * spinor_block_bytes(g, WL_F64));
     for (int k = 0; k < kVec64; ++k, p += f64) ws.v64[k] = p;
     if (flags & WL_MIXED) {
         ws.gauge32 = p;
-        p += align_up(gauge_bytes(g, WL_F32, flags & WL_LINK12));
-        const size_t f32 = align_up(2 * spinor_block_bytes(g, WL_F32));
+        p += align_up(gauge_bytes(g, lo_prec(flags), flags & WL_LINK12));
+        const size_t f32 = align_up(2 * spinor_block_bytes(g, lo_prec(flags)));
         for (int k = 0; k < kVec32; ++k, p += f32) ws.v32[k] = p;
     }
     return ws;
@@ -108,7 +113,6 @@ struct Space {
     bool eo;
     hipStream_t s;
     Scalars *sc;
-    unsigned *counter;
     double *partials;
     void *tmp;               // one parity block for the eo intermediate
     // model cost bookkeeping
@@ -121,7 +125,7 @@ struct Space {
         return static_cast<const char *>(full) + q * blk();
     }
 
-    Reduce red(int epi) const { return Reduce{partials, counter, sc->sums, epi, sc}; }
+    Reduce red(int epi) const { return Reduce{partials, sc->sums, epi, sc}; }
 
     // out = A in, A = M (full) or Mhat_e (eo), or the adjoint; optional fused
     // reduction (norm of out / <aux, out> / <out, in> and ||out||^2).
@@ -192,8 +196,9 @@ constexpr int kStallWindow = 2000;
 // ---------------------------------------------------------------------------
 struct CoreResult {
     int iters;
-    int status;   // WL_OK (target met), WL_NOCONV, WL_BREAKDOWN
+    int status;   // WL_OK (target met), WL_NOCONV, WL_BREAKDOWN, WL_STAGNATED
     double rr;
+    int updates = 0;   // reliable updates (mixed CG)
 };
 
 static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, void *t, void *q,
@@ -223,6 +228,103 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
     res.iters = h.iter;
     res.rr = h.rr;
     res.status = h.done ? h.status : WL_NOCONV;
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision CGNR with reliable updates. CG iterates in the FP32 space
+// k32 on (r, p, x_lo); once ||r||^2 has dropped by delta^2 since the last
+// update (the device loop stops itself there), the FP32 correction x_lo is
+// added to the FP64 solution x, the normal-equations residual
+// A^dag (rhs - A x) is recomputed in FP64 and copied back into r, and the
+// iteration continues along the same search direction p.
+// ---------------------------------------------------------------------------
+struct LoVecs {
+    void *r, *p, *t, *q, *x;
+};
+
+// residual reduction between reliable updates, per inner precision
+static double reliable_delta(int prec) { return prec == WL_F16S ? 0.2 : 0.1; }
+
+static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, void *r64,
+                              void *t64, const LoVecs &lo, double target, double delta,
+                              int maxit) {
+    const int npar = k64.npar();
+    const int chunk = chunk_for(*k64.g);
+    auto residual64 = [&]() {
+        k64.apply(x, t64, false, kEpiNone, nullptr, nullptr);
+        k64.blas(kOpXmy, const_cast<void *>(rhs), t64, nullptr, nullptr, nullptr, nullptr,
+                 kEpiNone, false);
+        k64.apply(t64, r64, true, kEpiNone, nullptr, nullptr);
+        return k64.norm2(r64);
+    };
+    // load the FP64 residual into r, clear x_lo, and set the device stop point
+    auto reload = [&](double rr) {
+        check(launch_convert_spinor(*k64.g, npar, WL_F64, r64, k32.prec, lo.r, k64.s));
+        k32.blas(kOpZero, lo.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        check(launch_set_target(k32.sc, std::max(target, delta * delta * rr), k32.s));
+    };
+    CoreResult res{0, WL_NOCONV, 0.0, 0};
+    double rr = residual64();
+    res.rr = rr;
+    if (!std::isfinite(rr)) {
+        res.status = WL_BREAKDOWN;
+        return res;
+    }
+    if (rr <= target) {
+        res.status = WL_OK;
+        return res;
+    }
+    reload(rr);
+    k32.blas(kOpCopyNorm2, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+    int its = 0, stale = 0;
+    while (its < maxit) {
+        Scalars h = read_scalars(k32.sc, k32.s);
+        while (!h.done && its + h.iter < maxit) {
+            const int n = std::min(chunk, maxit - its - h.iter);
+            for (int it = 0; it < n; ++it) {
+                const int *skip = &k32.sc->done;
+                k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
+                k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
+                k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
+                k32.blas(kOpCgP, lo.r, lo.p);
+            }
+            h = read_scalars(k32.sc, k32.s);
+        }
+        its += h.iter;
+        // reliable update: x += x_lo in FP64, fresh FP64 residual
+        check(launch_accum_lo(*k64.g, npar, k32.prec, lo.x, x, k64.s));
+        const double rr_new = residual64();
+        res.updates += 1;
+        res.rr = rr_new;
+        if (!std::isfinite(rr_new)) {
+            res.status = WL_BREAKDOWN;
+            break;
+        }
+        if (rr_new <= target) {
+            res.status = WL_OK;
+            break;
+        }
+        stale = rr_new < 0.5 * rr ? 0 : stale + 1;
+        if (stale > 8) {
+            res.status = WL_STAGNATED;
+            break;
+        }
+        rr = rr_new;
+        reload(rr);
+        // sc->rr = ||r||^2 of the reloaded residual
+        k32.blas(kOpNorm2, lo.r, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+        // The device loop stopped right after the x, r update, so the direction
+        // update of that iteration was skipped: apply it now with the reloaded
+        // residual, beta = ||r||^2 / ||r_old||^2 (||r_old||^2 = rr / beta).
+        if (h.done && h.status == WL_OK && h.beta > 0.0 && h.rr > 0.0) {
+            check(launch_beta_ratio(k32.sc, h.rr / h.beta, k32.s));
+            k32.blas(kOpCgP, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        } else {   // broken down or out of iterations: restart the direction from r
+            k32.blas(kOpCopy, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        }
+    }
+    res.iters = its;
     return res;
 }
 
@@ -311,10 +413,16 @@ struct Cost {
     double flops, bytes;
 };
 
+// bytes of one stored spinor site and one stored link
+static double site_bytes(int prec) { return prec == WL_F64 ? 192.0 : prec == WL_F32 ? 96.0 : 52.0; }
+static double link_bytes(int prec, bool link12) {
+    return (prec == WL_F64 ? 16.0 : prec == WL_F32 ? 8.0 : 4.0) * (link12 ? 6 : 9);
+}
+
 static Cost apply_cost(const Geom &g, int prec, bool link12, bool eo) {
     const double V = 2.0 * g.Vh;
-    const double sp = prec == WL_F64 ? 192.0 : 96.0;
-    const double ln = (prec == WL_F64 ? 16.0 : 8.0) * (link12 ? 6 : 9);
+    const double sp = site_bytes(prec);
+    const double ln = link_bytes(prec, link12);
     if (!eo) return {1368.0 * V, V * (2 * sp + 4 * ln)};
     // two half hops over V/2 sites each; the second adds the xpay read
     return {(2 * 1320.0 + 48.0) * V / 2, V / 2 * (2 * (2 * sp + 8 * ln) + sp)};
@@ -323,7 +431,7 @@ static Cost apply_cost(const Geom &g, int prec, bool link12, bool eo) {
 static Cost iter_cost(const Geom &g, int prec, bool link12, bool eo, bool bicg) {
     const Cost a = apply_cost(g, prec, link12, eo);
     const double Vs = eo ? g.Vh : 2.0 * g.Vh;
-    const double sp = prec == WL_F64 ? 192.0 : 96.0;
+    const double sp = site_bytes(prec);
     // CG: 2 applies + CgXR (4 reads, 2 writes) + CgP (2 reads, 1 write)
     // BiCGStab: 2 applies (+1 aux read) + BiP (3r 1w) + BiS (2r 1w) + BiXR (5r 2w)
     const double vec = bicg ? (1 + 4 + 3 + 7) : (6 + 3);
@@ -344,14 +452,12 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
     const bool mixed = in.flags & WL_MIXED;
     Workspace ws = carve(g, in.flags, in.work);
 
-    Space full64{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, ws.sc, ws.counter,
+    Space full64{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, ws.sc,
                  ws.partials, nullptr};
     wl_solve_stats out{};
     double flops = 0, bytes = 0;
     int status = WL_NOCONV;
     try {
-        // counters must start at zero; the scalar block is rewritten by every core
-        check(hipMemsetAsync(ws.counter, 0, 64, in.s));
         if (!(in.flags & WL_X0))
             full64.blas(kOpZero, in.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
         const double b2 = full64.norm2(in.b);
@@ -372,14 +478,20 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
             double r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
             flops += tr.flops;
             bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
-            int total_it = 0, restarts = 0;
+            int total_it = 0, restarts = 0, reliable = 0;
             double best_r2 = r2;
             int since_best = 0;
 
-            if (!mixed) {
-                // Krylov directly in FP64 on the caller's x (even block for eo)
-                Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, ws.sc, ws.counter,
+            if (!(mixed && bicg)) {
+                // Krylov on the caller's x (even block for eo): plain FP64, or
+                // FP32 iterations with reliable FP64 updates (mixed CG)
+                Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, ws.sc,
                         ws.partials, ws.v64[7]};
+                const int lo = lo_prec(in.flags);
+                Space k32{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
+                          ws.partials, ws.v32[7]};
+                if (mixed)
+                    check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
                 void *rhs = const_cast<void *>(in.b);
                 if (eo) {
                     eo_source(k, in.b, ws.v64[5]);
@@ -398,14 +510,25 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
                     if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
                     CoreResult cr;
                     const int left = in.maxiter - total_it;
-                    if (!bicg)
-                        cr = cg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2], ws.v64[3],
-                                     eta * eta * mb2, left);
-                    else
+                    if (bicg) {
                         cr = bicg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2],
                                        ws.v64[3], ws.v64[4], ws.v64[6], eta * eta * rhs2, left);
+                    } else if (mixed) {
+                        const LoVecs lv{ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3], ws.v32[6]};
+                        cr = cg_reliable(k, k32, rhs, in.x, ws.v64[0], ws.v64[2], lv,
+                                         eta * eta * mb2, reliable_delta(lo), left);
+                        const Cost u = apply_cost(g, WL_F64, link12, eo);
+                        const double Vs = eo ? g.Vh : 2.0 * g.Vh;
+                        flops += cr.updates * 2 * u.flops;
+                        bytes += cr.updates * (2 * u.bytes +
+                                               Vs * (6 * 192.0 + 3 * site_bytes(lo)));
+                        reliable += cr.updates;
+                    } else {
+                        cr = cg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2], ws.v64[3],
+                                     eta * eta * mb2, left);
+                    }
                     total_it += cr.iters;
-                    const Cost c = iter_cost(g, WL_F64, link12, eo, bicg);
+                    const Cost c = iter_cost(g, mixed ? lo : WL_F64, link12, eo, bicg);
                     flops += c.flops * cr.iters;
                     bytes += c.bytes * cr.iters;
                     if (eo) eo_reconstruct(k, in.b, in.x);
@@ -423,17 +546,23 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
                     }
                 }
             } else {
-                // FP64 defect correction around FP32 Krylov solves of M e = r
-                Space k{&g, WL_F32, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc, ws.counter,
+                // FP64 defect correction around FP32 BiCGStab solves of M e = r;
+                // each inner solve aims at 1e-5 relative, or less when that
+                // would overshoot the final tolerance
+                const int lo = lo_prec(in.flags);
+                Space k{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
                         ws.partials, ws.v32[7]};
-                check(launch_convert_gauge(g, link12, in.gauge, ws.gauge32, in.s));
-                const double delta = 1e-5;
+                check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
+                // the precision floor of the inner solve: FP16 storage cannot
+                // reach 1e-5 relative
+                const double floor = lo == WL_F16S ? 1e-2 : 1e-5;
                 while (true) {
+                    const double delta = std::max(floor, 0.3 * std::sqrt(tol2 / r2));
                     if (r2 <= tol2) { status = WL_OK; break; }
                     if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
                     if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
-                    // r64 (in v64[6]) -> r32 (v32[5]); e32 (v32[6]) = 0
-                    check(launch_convert_spinor(g, 2, WL_F64, ws.v64[6], WL_F32, ws.v32[5], in.s));
+                    // r64 (in v64[6]) -> r_lo (v32[5]); e_lo (v32[6]) = 0
+                    check(launch_convert_spinor(g, 2, WL_F64, ws.v64[6], lo, ws.v32[5], in.s));
                     k.eo = false;
                     k.blas(kOpZero, ws.v32[6], nullptr, nullptr, nullptr, nullptr, nullptr,
                            kEpiNone, false);
@@ -444,24 +573,16 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
                         rhs = ws.v32[4];
                     }
                     const int left = in.maxiter - total_it;
-                    CoreResult cr;
-                    if (!bicg) {
-                        k.apply(rhs, ws.v32[2], true, kEpiNone, nullptr, nullptr);
-                        const double mb2 = k.norm2(ws.v32[2]);
-                        cr = cg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3],
-                                     delta * delta * mb2, left);
-                    } else {
-                        const double rhs2 = k.norm2(rhs);
-                        cr = bicg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2],
-                                       ws.v32[3], ws.v32[8], ws.v32[9], delta * delta * rhs2,
-                                       left);
-                    }
+                    const double rhs2 = k.norm2(rhs);
+                    const CoreResult cr =
+                        bicg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3],
+                                  ws.v32[8], ws.v32[9], delta * delta * rhs2, left);
                     total_it += cr.iters;
-                    const Cost c = iter_cost(g, WL_F32, link12, eo, bicg);
+                    const Cost c = iter_cost(g, lo, link12, eo, bicg);
                     flops += c.flops * cr.iters;
                     bytes += c.bytes * cr.iters;
                     if (eo) eo_reconstruct(k, ws.v32[5], ws.v32[6]);
-                    check(launch_accum_f32(g, 2, ws.v32[6], in.x, in.s));
+                    check(launch_accum_lo(g, 2, lo, ws.v32[6], in.x, in.s));
                     r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
                     flops += tr.flops;
                     bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
@@ -473,6 +594,7 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
             }
             out.iterations = total_it;
             out.restarts = restarts;
+            out.reliable_updates = reliable;
             out.true_res = std::sqrt(r2 / b2);
         }
         check(hipStreamSynchronize(in.s));

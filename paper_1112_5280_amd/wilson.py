@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libwilson.so")
 # flags (wilson.h)
 F64 = 0x0
 F32 = 0x1
+F16S = 0x2
 LINK18 = 0x0
 LINK12 = 0x4
 DAG = 0x8
@@ -53,7 +54,7 @@ class WilsonError(RuntimeError):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("restarts", ctypes.c_int32), ("op_applies", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 

@@ -5,7 +5,12 @@ import torch
 # Bars from the problem statement: FP64 operators agree with the FP64 oracle to
 # 1e-13 relative; FP32 to 1e-6. Both the field-norm ratio and the max-abs ratio
 # must meet them (sites can be near zero, so no per-site relative error).
-TOL = {0x0: 1e-13, 0x1: 1e-6}
+# FP16 storage has no stated bar; binary16's unit roundoff is 2^-11 = 4.9e-4,
+# the inputs are rounded once (spinors relative to their site maximum, links
+# absolutely), the 12-real rebuild multiplies two rounded entries, and the
+# output is rounded once more, so the error is a few units of 4.9e-4: the bar
+# 3e-3 allows six.
+TOL = {0x0: 1e-13, 0x1: 1e-6, 0x2: 3e-3}
 
 
 def errs(got, want):

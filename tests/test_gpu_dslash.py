@@ -36,7 +36,7 @@ def _fields(dims, seed):
 
 
 @pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
-@pytest.mark.parametrize("prec", [0x0, 0x1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0x0, 0x1, 0x2], ids=["f64", "f32", "f16s"])
 @pytest.mark.parametrize("link", [0x0, 0x4], ids=["link18", "link12"])
 @pytest.mark.parametrize("phases", PHASES, ids=["antiperiodic", "twisted"])
 def test_full_operator(w, dims, prec, link, phases):
@@ -57,7 +57,7 @@ def test_full_operator(w, dims, prec, link, phases):
 
 
 @pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
-@pytest.mark.parametrize("prec", [0x0, 0x1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [0x0, 0x1, 0x2], ids=["f64", "f32", "f16s"])
 @pytest.mark.parametrize("link", [0x0, 0x4], ids=["link18", "link12"])
 def test_even_odd(w, dims, prec, link):
     kappa = 0.141
@@ -93,6 +93,11 @@ def test_pack_roundtrip(w):
     assert np.array_equal(got, psi)
     got32 = gu.to_np(w.unpack_spinor(w.pack_spinor(psi, dims, w.F32), dims, w.F32))
     assert np.array_equal(got32, psi.astype(np.complex64).astype(np.complex128))
+    # FP16 storage: each component within half a binary16 ulp of the site maximum
+    got16 = gu.to_np(w.unpack_spinor(w.pack_spinor(psi, dims, w.F16S), dims, w.F16S))
+    smax = np.maximum(np.abs(psi.real), np.abs(psi.imag)).reshape(len(psi), -1).max(1)
+    err = np.maximum(np.abs((got16 - psi).real), np.abs((got16 - psi).imag))
+    assert (err.reshape(len(psi), -1).max(1) <= smax * 2.0 ** -11 * (1 + 1e-6)).all()
 
 
 def test_free_field_plane_wave_on_gpu(w):

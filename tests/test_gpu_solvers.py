@@ -36,6 +36,7 @@ SOLVES = [
     ("cg", 0x0), ("cg", 0x20), ("cg", 0x40), ("cg", 0x60), ("cg", 0x4 | 0x20),
     ("bicgstab", 0x0), ("bicgstab", 0x20), ("bicgstab", 0x40), ("bicgstab", 0x60),
     ("bicgstab", 0x4 | 0x60),
+    ("cg", 0x2 | 0x60), ("cg", 0x2 | 0x4 | 0x60), ("bicgstab", 0x2 | 0x60),
 ]
 
 
@@ -44,7 +45,7 @@ def _name(s):
     parts = [solver]
     parts.append("eo" if f & 0x20 else "full")
     if f & 0x40:
-        parts.append("mixed")
+        parts.append("mixed-f16" if f & 0x2 else "mixed")
     if f & 0x4:
         parts.append("link12")
     return "-".join(parts)
@@ -64,6 +65,8 @@ def test_config1_solves(w, cfg1, solve):
     B = w.pack_spinor(b, dims)
     X = w.empty_spinor(dims)
     st = _solve(w, solver, G, B, X, dims, kappa, flags)
+    if flags & 0x40:
+        assert st["reliable_updates"] > 0 or solver == "bicgstab"
     assert st["status"] == 0, st
     x = gu.to_np(w.unpack_spinor(X, dims))
     res = oracle.true_residual(U, b, x, dims, kappa)
@@ -73,9 +76,10 @@ def test_config1_solves(w, cfg1, solve):
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= cond * 1.2e-10
 
 
-@pytest.mark.parametrize("solve", [("cg", 0x20), ("cg", 0x60), ("bicgstab", 0x20),
-                                   ("bicgstab", 0x60)],
-                         ids=["cg-eo", "cg-eo-mixed", "bicgstab-eo", "bicgstab-eo-mixed"])
+@pytest.mark.parametrize("solve", [("cg", 0x20), ("cg", 0x60), ("cg", 0x62),
+                                   ("bicgstab", 0x20), ("bicgstab", 0x60)],
+                         ids=["cg-eo", "cg-eo-mixed", "cg-eo-mixed-f16", "bicgstab-eo",
+                              "bicgstab-eo-mixed"])
 def test_smooth_field_solves(w, solve):
     """8^3 x 16, exp(i eps H) links with eps = 0.3, kappa = 0.15 (past the
     spectrum's crossing of Re = 0 for these fields: CG must converge; BiCGStab
