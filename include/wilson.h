@@ -182,6 +182,29 @@ int solve_bicgstab(const void *gauge, const void *b, void *x,
                    double tol, int32_t maxiter, uint32_t flags, void *work,
                    size_t work_bytes, wl_solve_stats *stats, void *stream);
 
+/* Batched operator: `in` and `out` each hold nrhs packed full spinors one
+ * after another (stride wl_spinor_bytes(dims, flags, 2)); the modes are those
+ * of wilson_dslash. All nrhs fields share the gauge field, whose links are
+ * fetched from memory once per site and reused from cache for the others
+ * (paper Sec. 4: the 12 spin-colour point sources of one propagator).
+ * Asynchronous on `stream`; in and out must not overlap. */
+int wilson_dslash_batch(const void *gauge, const void *in, void *out, int32_t nrhs,
+                        const int32_t dims[4], double kappa, const double phases[8],
+                        uint32_t flags, void *stream);
+
+/* Batched CGNR: solve M x_r = b_r for 1 <= nrhs <= 64 right-hand sides on one
+ * gauge field together. b and x each hold nrhs packed FP64 full spinors one
+ * after another; flags as for solve_cg (FP64; WL_EO, WL_LINK12, WL_X0) --
+ * WL_MIXED is not supported here (WL_EINVAL). Each RHS has its own Krylov
+ * scalars, stops at its own tolerance and is restarted on its own FP64 true
+ * residual; `stats` (host, may be NULL) receives nrhs entries. `work` needs
+ * wl_workspace_bytes(dims, flags, nrhs) bytes. Returns WL_OK when every RHS
+ * met tol, else a non-OK status of some RHS (see stats). Blocks until done. */
+int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
+                   const int32_t dims[4], double kappa, const double phases[8],
+                   double tol, int32_t maxiter, uint32_t flags, void *work,
+                   size_t work_bytes, wl_solve_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

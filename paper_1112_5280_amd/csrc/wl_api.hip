@@ -258,8 +258,89 @@ int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t
 size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs) {
     Geom g;
     std::string why;
-    if (!make_geom(dims, &g, &why) || nrhs < 1) return 0;
-    return workspace_bytes(g, flags) * size_t(nrhs);
+    if (!make_geom(dims, &g, &why) || nrhs < 1 || nrhs > kMaxBatch) return 0;
+    return nrhs == 1 ? workspace_bytes(g, flags) : workspace_bytes_batch(g, flags, nrhs);
+}
+
+int wilson_dslash_batch(const void *gauge, const void *in, void *out, int32_t nrhs,
+                        const int32_t dims[4], double kappa, const double phases[8],
+                        uint32_t flags, void *stream) {
+    Geom g;
+    Phases ph;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why) ||
+        !get_phases(phases, &ph, &why))
+        return fail(WL_EINVAL, why);
+    if (!gauge || !in || !out) return fail(WL_EINVAL, "NULL buffer");
+    if (nrhs < 1 || nrhs > 65536) return fail(WL_EINVAL, "nrhs must be in 1..65536");
+    const size_t blk = spinor_block_bytes(g, prec);
+    const size_t fs = 2 * blk;
+    const char *ib = static_cast<const char *>(in);
+    const char *ob = static_cast<const char *>(out);
+    if (ib < ob + fs * nrhs && ob < ib + fs * nrhs) return fail(WL_EINVAL, "in and out overlap");
+    if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    HopCall c{};
+    c.gauge = gauge;
+    c.in[0] = in;
+    c.in[1] = ib + blk;
+    c.out[0] = out;
+    c.out[1] = static_cast<char *>(out) + blk;
+    if (!(flags & WL_HOP)) {
+        c.xs[0] = c.in[0];
+        c.xs[1] = c.in[1];
+        c.c = -kappa;
+    } else {
+        c.c = 1.0;
+    }
+    c.first_par = 0;
+    c.npar = 2;
+    c.dag = flags & WL_DAG;
+    c.nrhs = nrhs;
+    c.fstride = fs;
+    const hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c,
+                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_batch");
+}
+
+int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
+                   const int32_t dims[4], double kappa, const double phases[8], double tol,
+                   int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                   wl_solve_stats *stats, void *stream) {
+    SolveIn in{};
+    std::string why;
+    if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
+        return fail(WL_EINVAL, why);
+    if (nrhs < 1 || nrhs > kMaxBatch)
+        return fail(WL_EINVAL, "nrhs must be in 1.." + std::to_string(kMaxBatch));
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    if ((flags & WL_PREC_MASK) != WL_F64 || (flags & (WL_MIXED | WL_DAG | WL_HOP)))
+        return fail(WL_EINVAL, "batched solves are FP64 (no WL_MIXED, WL_DAG or WL_HOP)");
+    if (!gauge || !b || !x || !work) return fail(WL_EINVAL, "NULL buffer");
+    const size_t fs = 2 * spinor_block_bytes(in.g, WL_F64);
+    const char *bb = static_cast<const char *>(b);
+    const char *xb = static_cast<const char *>(x);
+    if (bb < xb + fs * nrhs && xb < bb + fs * nrhs) return fail(WL_EINVAL, "b and x overlap");
+    if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WL_EINVAL, "tol must be positive");
+    if (maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
+    const size_t need = workspace_bytes_batch(in.g, flags, nrhs);
+    if (work_bytes < need)
+        return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                       " bytes, got " + std::to_string(work_bytes));
+    in.gauge = gauge;
+    in.b = b;
+    in.x = x;
+    in.kappa = kappa;
+    in.tol = tol;
+    in.maxiter = maxiter;
+    in.flags = flags;
+    in.work = work;
+    in.s = static_cast<hipStream_t>(stream);
+    const int st = run_cg_batch(in, nrhs, stats, &why);
+    if (st != WL_OK) g_last_error = why.empty() ? "at least one right-hand side missed tol" : why;
+    return st;
 }
 
 static int solve_common(bool bicg, const void *gauge, const void *b, void *x,

@@ -468,6 +468,28 @@ hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s) {
     return hipGetLastError();
 }
 
+struct Targets {
+    double t[kMaxBatch];
+};
+
+__global__ void set_targets_kernel(Scalars *sc, Targets tg, int n) {
+    const int r = threadIdx.x;
+    if (blockIdx.x == 0 && r < n) {
+        sc[r].target = tg.t[r];
+        sc[r].done = 0;
+        sc[r].status = WL_OK;
+        sc[r].iter = 0;
+    }
+}
+
+hipError_t launch_set_targets(Scalars *sc, const double *targets, int n, hipStream_t s) {
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    Targets tg{};
+    for (int r = 0; r < n; ++r) tg.t[r] = targets[r];
+    hipLaunchKernelGGL(set_targets_kernel, dim3(1), dim3(kMaxBatch), 0, s, sc, tg, n);
+    return hipGetLastError();
+}
+
 __global__ void beta_ratio_kernel(Scalars *sc, double rr_old) {
     if (threadIdx.x == 0 && blockIdx.x == 0) sc->beta = sc->rr / rr_old;
 }

@@ -21,6 +21,7 @@ namespace wl {
 #endif
 constexpr int kBlock = WL_BLOCK; // threads per block of every site kernel (multiple of 64)
 constexpr int kMaxSums = 4;      // doubles per fused reduction
+constexpr int kMaxBatch = 64;    // right-hand sides per batched solve
 
 // ---------------------------------------------------------------------------
 // Lattice geometry of the packed layout
@@ -329,6 +330,8 @@ hipError_t launch_accum_lo(const Geom &g, int npar, int src_prec, const void *x,
 hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s);
 // CG direction update after a residual replacement: beta = sc->rr / rr_old
 hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s);
+// launch_set_target for RHS 0..n-1 of a batch (n <= kMaxBatch), host targets
+hipError_t launch_set_targets(Scalars *sc, const double *targets, int n, hipStream_t s);
 
 // ---- solvers ---------------------------------------------------------------
 size_t workspace_bytes(const Geom &g, uint32_t flags);
@@ -347,5 +350,9 @@ struct SolveIn {
 };
 
 int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why);
+
+// batched CG (FP64, full or even-odd): nrhs fields of b and x, st[nrhs]
+size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs);
+int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why);
 
 }  // namespace wl

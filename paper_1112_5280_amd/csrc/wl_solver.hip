@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "wl_internal.h"
 
@@ -117,6 +118,9 @@ struct Space {
     void *tmp;               // one parity block for the eo intermediate
     // model cost bookkeeping
     double applies = 0;      // applications of A or A^dag
+    // batches: nrhs fields per vector, fstride bytes apart; scalars sc[0..nrhs)
+    int nrhs = 1;
+    size_t fstride = 0;
 
     int npar() const { return eo ? 1 : 2; }
     size_t blk() const { return spinor_block_bytes(*g, prec); }
@@ -140,6 +144,7 @@ struct Space {
             c.aux[0] = aux; c.aux[1] = aux ? par(aux, 1) : nullptr;
             c.out[0] = out; c.out[1] = par(out, 1);
             c.first_par = 0; c.npar = 2; c.c = -kappa; c.dag = dag; c.skip = skip; c.red = rp;
+            c.nrhs = nrhs; c.fstride = fstride;
             check(launch_hop(*g, prec, link12, ph, c, s));
         } else {
             HopCall c1{};
@@ -147,6 +152,7 @@ struct Space {
             c1.in[0] = in;
             c1.out[1] = tmp;
             c1.first_par = 1; c1.npar = 1; c1.c = 1.0; c1.dag = dag; c1.skip = skip;
+            c1.nrhs = nrhs; c1.fstride = fstride;
             check(launch_hop(*g, prec, link12, ph, c1, s));
             HopCall c2{};
             c2.gauge = gauge;
@@ -156,6 +162,7 @@ struct Space {
             c2.out[0] = out;
             c2.first_par = 0; c2.npar = 1; c2.c = -kappa * kappa; c2.dag = dag; c2.skip = skip;
             c2.red = rp;
+            c2.nrhs = nrhs; c2.fstride = fstride;
             check(launch_hop(*g, prec, link12, ph, c2, s));
         }
         applies += 1;
@@ -174,6 +181,8 @@ struct Space {
         c.skip = use_skip ? &sc->done : nullptr;
         c.red = (op == kOpNorm2 || op == kOpXmy || op == kOpCgXR || op == kOpBiXR ||
                  op == kOpCopyNorm2 || op == kOpCopy2Norm2) ? &r : nullptr;
+        c.nrhs = nrhs;
+        c.fstride = fstride;
         check(launch_blas(*g, prec, c, s));
     }
 
@@ -383,6 +392,7 @@ static void eo_source(Space &k, const void *b_full, void *bhat_e) {
     c.xs[0] = b_full;
     c.out[0] = bhat_e;
     c.first_par = 0; c.npar = 1; c.c = k.kappa; c.dag = false;
+    c.nrhs = k.nrhs; c.fstride = k.fstride;
     check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
 }
 
@@ -394,6 +404,7 @@ static void eo_reconstruct(Space &k, const void *b_full, void *x_full) {
     c.xs[1] = k.par(b_full, 1);
     c.out[1] = k.par(x_full, 1);
     c.first_par = 1; c.npar = 1; c.c = k.kappa; c.dag = false;
+    c.nrhs = k.nrhs; c.fstride = k.fstride;
     check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
 }
 
@@ -610,6 +621,206 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
     out.bytes = bytes;
     if (st) *st = out;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// Batched CGNR: nrhs right-hand sides on one lattice, solved together (the 12
+// spin-colour point sources of one propagator are such a batch). Every kernel
+// of an iteration covers all RHS, with the RHS index fastest in the block
+// order, so each link is fetched from HBM once per site and re-served from L2
+// to the other RHS. Each RHS owns a Scalars block: its own alpha, beta, stop
+// flag and target, so it stops on its own; true residuals and restarts are
+// per RHS as in the single solve.
+// ---------------------------------------------------------------------------
+static size_t batch_header_bytes(const Geom &g, int nrhs) {
+    return align_up(size_t(nrhs) * sizeof(Scalars) + 4096) +
+           align_up(sizeof(double) * kMaxSums * 2 * size_t(g.bpp) * nrhs);
+}
+
+size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs) {
+    return batch_header_bytes(g, nrhs) +
+           kVec64 * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, WL_F64));
+}
+
+static void read_scalars_n(const Scalars *dev, int n, hipStream_t s, Scalars *out) {
+    thread_local Scalars *h = nullptr;
+    if (!h) check(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Scalars) * kMaxBatch,
+                                hipHostMallocDefault));
+    check(hipMemcpyAsync(h, dev, sizeof(Scalars) * n, hipMemcpyDeviceToHost, s));
+    check(hipStreamSynchronize(s));
+    std::memcpy(out, h, sizeof(Scalars) * n);
+}
+
+static void norm2_n(Space &k, const void *v, double *out) {
+    k.blas(kOpNorm2, const_cast<void *>(v), nullptr, nullptr, nullptr, nullptr, nullptr,
+           kEpiNone, false);
+    Scalars h[kMaxBatch];
+    read_scalars_n(k.sc, k.nrhs, k.s, h);
+    for (int r = 0; r < k.nrhs; ++r) out[r] = h[r].sums[0];
+}
+
+// CG iterations for every RHS until each meets its own target (or maxit)
+static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, void *t, void *q,
+                          const double *targets, int maxit, int *iters) {
+    check(launch_set_targets(k.sc, targets, k.nrhs, k.s));
+    k.apply(x, t, false, kEpiNone, nullptr, nullptr);
+    k.blas(kOpXmy, const_cast<void *>(rhs), t, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    k.apply(t, r, true, kEpiNone, nullptr, nullptr);
+    k.blas(kOpCopyNorm2, r, p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+    const int chunk = chunk_for(*k.g);
+    Scalars h[kMaxBatch];
+    read_scalars_n(k.sc, k.nrhs, k.s, h);
+    auto all_done = [&]() {
+        for (int i = 0; i < k.nrhs; ++i)
+            if (!h[i].done && h[i].iter < maxit) return false;
+        return true;
+    };
+    int done_it = 0;
+    while (!all_done() && done_it < maxit) {
+        const int n = std::min(chunk, maxit - done_it);
+        for (int it = 0; it < n; ++it) {
+            const int *skip = &k.sc->done;
+            k.apply(p, t, false, kEpiCgPap, nullptr, skip);
+            k.apply(t, q, true, kEpiNone, nullptr, skip);
+            k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+            k.blas(kOpCgP, r, p);
+        }
+        done_it += n;
+        read_scalars_n(k.sc, k.nrhs, k.s, h);
+    }
+    for (int i = 0; i < k.nrhs; ++i) iters[i] = h[i].iter;
+}
+
+int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = in.g;
+    const bool eo = in.flags & WL_EO;
+    const bool link12 = in.flags & WL_LINK12;
+    const size_t fs = align_up(2 * spinor_block_bytes(g, WL_F64));   // == the caller's stride
+    char *base = static_cast<char *>(in.work);
+    Scalars *sc = reinterpret_cast<Scalars *>(base);
+    double *partials = reinterpret_cast<double *>(
+        base + align_up(size_t(nrhs) * sizeof(Scalars) + 4096));
+    char *v[kVec64];
+    char *p = base + batch_header_bytes(g, nrhs);
+    for (int i = 0; i < kVec64; ++i, p += fs * nrhs) v[i] = p;
+
+    Space full{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, sc, partials, nullptr};
+    full.nrhs = nrhs;
+    full.fstride = fs;
+    Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, sc, partials, v[7]};
+    k.nrhs = nrhs;
+    k.fstride = fs;
+
+    std::vector<double> b2(nrhs), r2(nrhs), mb2(nrhs), eta(nrhs, in.tol), targets(nrhs);
+    std::vector<int> iters(nrhs, 0), total(nrhs, 0), restarts(nrhs, 0), status(nrhs, WL_NOCONV);
+    std::vector<int> since_best(nrhs, 0);
+    std::vector<double> best(nrhs);
+    double flops = 0, bytes = 0;
+    int ret = WL_OK;
+    const Cost tr = apply_cost(g, WL_F64, link12, false);
+    const Cost ic = iter_cost(g, WL_F64, link12, eo, false);
+    auto true_res = [&]() {
+        full.apply(in.x, v[6], false, kEpiNone, nullptr, nullptr);
+        full.blas(kOpXmy, const_cast<void *>(in.b), v[6], nullptr, nullptr, nullptr, nullptr,
+                  kEpiNone, false);
+        Scalars h[kMaxBatch];
+        read_scalars_n(sc, nrhs, in.s, h);
+        for (int r = 0; r < nrhs; ++r) r2[r] = h[r].sums[0];
+        flops += nrhs * tr.flops;
+        bytes += nrhs * (tr.bytes + 3.0 * 2 * g.Vh * 192.0);
+    };
+    try {
+        if (!(in.flags & WL_X0))
+            full.blas(kOpZero, in.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        norm2_n(full, in.b, b2.data());
+        true_res();
+        void *rhs = const_cast<void *>(in.b);
+        if (eo) {
+            eo_source(k, in.b, v[5]);
+            rhs = v[5];
+        }
+        k.apply(rhs, v[2], true, kEpiNone, nullptr, nullptr);
+        norm2_n(k, v[2], mb2.data());
+        std::vector<char> active(nrhs, 1);
+        for (int r = 0; r < nrhs; ++r) {
+            best[r] = r2[r];
+            if (b2[r] == 0.0) {   // b = 0: x = 0 is exact
+                Space one = full;
+                one.nrhs = 1;
+                one.sc = sc + r;
+                one.blas(kOpZero, static_cast<char *>(in.x) + r * fs, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, kEpiNone, false);
+                r2[r] = 0.0;
+                status[r] = WL_OK;
+                active[r] = 0;
+            }
+        }
+        while (true) {
+            bool any = false;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!active[r]) continue;
+                const double tol2 = in.tol * in.tol * b2[r];
+                int s = -1;
+                if (!std::isfinite(b2[r]) || !std::isfinite(r2[r])) s = WL_BREAKDOWN;
+                else if (r2[r] <= tol2) s = WL_OK;
+                else if (total[r] >= in.maxiter) s = WL_NOCONV;
+                else if (restarts[r] > kMaxRestarts || since_best[r] > 3) s = WL_STAGNATED;
+                if (s >= 0) {
+                    status[r] = s;
+                    active[r] = 0;
+                } else {
+                    any = true;
+                }
+            }
+            if (!any) break;
+            int left = 0;
+            for (int r = 0; r < nrhs; ++r) {
+                // an RHS that is finished gets a target it already meets: its kernels idle
+                targets[r] = active[r] ? eta[r] * eta[r] * mb2[r] : HUGE_VAL;
+                if (active[r]) left = std::max(left, in.maxiter - total[r]);
+            }
+            cg_core_batch(k, rhs, in.x, v[0], v[1], v[2], v[3], targets.data(), left, iters.data());
+            for (int r = 0; r < nrhs; ++r) {
+                total[r] += iters[r];
+                flops += ic.flops * iters[r];
+                bytes += ic.bytes * iters[r];
+            }
+            if (eo) eo_reconstruct(k, in.b, in.x);
+            true_res();
+            for (int r = 0; r < nrhs; ++r) {
+                if (!active[r]) continue;
+                if (r2[r] < 0.5 * best[r]) { best[r] = r2[r]; since_best[r] = 0; }
+                else ++since_best[r];
+                if (r2[r] > in.tol * in.tol * b2[r]) {
+                    ++restarts[r];
+                    const double rho = std::sqrt(r2[r] / b2[r]);
+                    eta[r] = std::max(eta[r] * (in.tol / rho) * 0.5, 1e-17);
+                }
+            }
+        }
+        check(hipStreamSynchronize(in.s));
+    } catch (const Fail &f) {
+        *why = std::string("HIP error in solver: ") + hipGetErrorString(f.err);
+        hipStreamSynchronize(in.s);
+        for (int r = 0; r < nrhs; ++r) status[r] = WL_EHIP;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int r = 0; r < nrhs; ++r) {
+        if (st) {
+            st[r] = wl_solve_stats{};
+            st[r].status = status[r];
+            st[r].iterations = total[r];
+            st[r].restarts = restarts[r];
+            st[r].true_res = b2[r] > 0.0 ? std::sqrt(r2[r] / b2[r]) : 0.0;
+            st[r].seconds = secs;
+            st[r].flops = flops / nrhs;
+            st[r].bytes = bytes / nrhs;
+        }
+        if (status[r] < 0) ret = status[r];
+        else if (ret == WL_OK) ret = status[r];
+    }
+    return ret;
 }
 
 }  // namespace wl

@@ -43,7 +43,7 @@ ANTIPERIODIC_T = (1.0, 1.0, 1.0, -1.0)
 SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor",
            "wilson_dslash", "wilson_dslash_eo", "wl_workspace_bytes",
-           "solve_cg", "solve_bicgstab")
+           "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch")
 
 
 class WilsonError(RuntimeError):
@@ -88,6 +88,11 @@ def _load():
         f.argtypes = [P, P, P, P, D, P, D, I32, U32, P, SZ,
                       ctypes.POINTER(SolveStats), P]
         f.restype = ctypes.c_int
+    lib.wilson_dslash_batch.argtypes = [P, P, P, I32, P, D, P, U32, P]
+    lib.wilson_dslash_batch.restype = ctypes.c_int
+    lib.solve_cg_batch.argtypes = [P, P, P, I32, P, D, P, D, I32, U32, P, SZ,
+                                   ctypes.POINTER(SolveStats), P]
+    lib.solve_cg_batch.restype = ctypes.c_int
     return lib
 
 
@@ -251,6 +256,44 @@ def solve_bicgstab(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
     """BiCGStab solve of M x = b (packed FP64 b, x); returns the stats dict."""
     return _solve(lib.solve_bicgstab, "solve_bicgstab", gauge, b, x, dims, kappa, phases,
                   tol, maxiter, flags, work, stream)
+
+
+def empty_batch(dims, nrhs, flags=F64, device="cuda"):
+    """nrhs packed full spinors stored one after another."""
+    return torch.empty(nrhs * spinor_bytes(dims, flags, 2), dtype=torch.uint8, device=device)
+
+
+def batch_field(batch, dims, flags, r):
+    """View of field r of a batch."""
+    n = spinor_bytes(dims, flags, 2)
+    return batch[r * n:(r + 1) * n]
+
+
+def wilson_dslash_batch(gauge, inp, out, nrhs, dims, kappa, phases=ANTIPERIODIC_T,
+                        flags=F64, stream=None):
+    """The operator of wilson_dslash on nrhs fields stored one after another."""
+    return _check(lib.wilson_dslash_batch(_ptr(gauge), _ptr(inp), _ptr(out), int(nrhs),
+                                          _dims(dims), float(kappa), _phases(phases), flags,
+                                          _stream(stream)), "wilson_dslash_batch")
+
+
+def solve_cg_batch(gauge, b, x, nrhs, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
+                   maxiter=100000, flags=F64, work=None, stream=None):
+    """Batched CGNR of nrhs right-hand sides; returns (status, [stats per RHS])."""
+    need = workspace_bytes(dims, flags, nrhs)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=b.device)
+    st = (SolveStats * int(nrhs))()
+    code = lib.solve_cg_batch(_ptr(gauge), _ptr(b), _ptr(x), int(nrhs), _dims(dims),
+                              float(kappa), _phases(phases), float(tol), int(maxiter), flags,
+                              _ptr(work), work.numel(), st, _stream(stream))
+    _check(code, "solve_cg_batch")
+    out = []
+    for s in st:
+        d = s.as_dict()
+        d["status_name"] = STATUS_NAMES.get(d["status"], "?")
+        out.append(d)
+    return code, out
 
 
 @dataclass
