@@ -80,6 +80,11 @@ extern "C" {
                                 (WL_F32, the default, or WL_F16S) inside an
                                 FP64 outer loop                               */
 #define WL_X0         0x80u  /* solvers: x holds the initial guess            */
+#define WL_GRAPH      0x100u /* solvers: capture each chunk of Krylov
+                                iterations once into a HIP graph and replay
+                                it (fewer launch overheads on small
+                                lattices); the solve waits for `stream` to
+                                drain, then runs on a library-owned stream */
 
 /* ---- status codes -------------------------------------------------------- */
 #define WL_OK          0

@@ -62,7 +62,7 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
-constexpr uint32_t kKnownFlags = WL_PREC_MASK | WL_LINK12 | WL_DAG | WL_HOP | WL_EO | WL_MIXED |
+constexpr uint32_t kKnownFlags = WL_PREC_MASK | WL_LINK12 | WL_DAG | WL_HOP | WL_EO | WL_MIXED | WL_GRAPH |
                                  WL_X0;
 
 bool get_prec(uint32_t flags, int *prec, std::string *why) {

@@ -121,6 +121,7 @@ struct Space {
     // batches: nrhs fields per vector, fstride bytes apart; scalars sc[0..nrhs)
     int nrhs = 1;
     size_t fstride = 0;
+    bool graph = false;      // replay chunks of Krylov iterations from a HIP graph
 
     int npar() const { return eo ? 1 : 2; }
     size_t blk() const { return spinor_block_bytes(*g, prec); }
@@ -198,6 +199,64 @@ struct Space {
 // large enough to hide the readback.
 static int chunk_for(const Geom &g) { return g.Vh >= (1 << 18) ? 4 : 16; }
 
+// ---------------------------------------------------------------------------
+// Chunks of Krylov iterations, enqueued directly or -- with WL_GRAPH --
+// captured once into a HIP graph and replayed for every later chunk of the
+// same length. A chunk holds kernel launches only (no memset, no host work);
+// the host reads the status block between replays.
+// ---------------------------------------------------------------------------
+struct ChunkRunner {
+    hipStream_t s;
+    bool graph;
+    int captured_n = -1;
+    hipGraphExec_t exec = nullptr;
+
+    ChunkRunner(hipStream_t s_, bool graph_) : s(s_), graph(graph_) {}
+    ChunkRunner(const ChunkRunner &) = delete;
+    ChunkRunner &operator=(const ChunkRunner &) = delete;
+    ~ChunkRunner() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+
+    template <class F>
+    void run(int n, F &&enqueue) {
+        if (!graph) {
+            enqueue(n);
+            return;
+        }
+        if (n != captured_n) {
+            if (exec) {
+                (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+                captured_n = -1;
+            }
+            check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipGraph_t gr = nullptr;
+            try {
+                enqueue(n);
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &gr);
+                if (gr) (void)hipGraphDestroy(gr);
+                throw;
+            }
+            check(hipStreamEndCapture(s, &gr));
+            const hipError_t e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            check(e);
+            captured_n = n;
+        }
+        check(hipGraphLaunch(exec, s));
+    }
+};
+
+// The library's own stream for captured solves (graphs cannot be captured on
+// the null stream); default priority, one per host thread.
+static hipStream_t graph_stream() {
+    thread_local hipStream_t s = nullptr;
+    if (!s) check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+}
+
 constexpr int kStallWindow = 2000;
 
 // ---------------------------------------------------------------------------
@@ -221,15 +280,18 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
     const int chunk = chunk_for(*k.g);
     int done_it = 0;
     Scalars h = read_scalars(k.sc, k.s);
+    ChunkRunner runner(k.s, k.graph);
     while (!h.done && done_it < maxit) {
         const int n = std::min(chunk, maxit - done_it);
-        for (int it = 0; it < n; ++it) {
-            const int *skip = &k.sc->done;
-            k.apply(p, t, false, kEpiCgPap, nullptr, skip);    // t = A p, pap = |t|^2
-            k.apply(t, q, true, kEpiNone, nullptr, skip);      // q = A^dag t
-            k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
-            k.blas(kOpCgP, r, p);
-        }
+        runner.run(n, [&](int m) {
+            for (int it = 0; it < m; ++it) {
+                const int *skip = &k.sc->done;
+                k.apply(p, t, false, kEpiCgPap, nullptr, skip);    // t = A p, pap = |t|^2
+                k.apply(t, q, true, kEpiNone, nullptr, skip);      // q = A^dag t
+                k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+                k.blas(kOpCgP, r, p);
+            }
+        });
         h = read_scalars(k.sc, k.s);
         done_it = h.iter;
     }
@@ -287,17 +349,20 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
     reload(rr);
     k32.blas(kOpCopyNorm2, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
     int its = 0, stale = 0;
+    ChunkRunner runner(k32.s, k32.graph);
     while (its < maxit) {
         Scalars h = read_scalars(k32.sc, k32.s);
         while (!h.done && its + h.iter < maxit) {
             const int n = std::min(chunk, maxit - its - h.iter);
-            for (int it = 0; it < n; ++it) {
-                const int *skip = &k32.sc->done;
-                k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
-                k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
-                k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
-                k32.blas(kOpCgP, lo.r, lo.p);
-            }
+            runner.run(n, [&](int m) {
+                for (int it = 0; it < m; ++it) {
+                    const int *skip = &k32.sc->done;
+                    k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
+                    k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
+                    k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
+                    k32.blas(kOpCgP, lo.r, lo.p);
+                }
+            });
             h = read_scalars(k32.sc, k32.s);
         }
         its += h.iter;
@@ -355,16 +420,19 @@ static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *r
     double best = h.rr;
     int best_it = 0;
     bool stalled = false;
+    ChunkRunner runner(k.s, k.graph);
     while (!h.done && h.iter < maxit) {
         const int n = std::min(chunk, maxit - h.iter);
-        for (int it = 0; it < n; ++it) {
-            const int *skip = &k.sc->done;
-            k.blas(kOpBiP, r, p, v);                               // p = r + b (p - w v)
-            k.apply(p, v, false, kEpiBiAlpha, rh, skip);           // v = A p, alpha
-            k.blas(kOpBiS, r, v, sv);                              // s = r - alpha v
-            k.apply(sv, t, false, kEpiBiOmega, nullptr, skip);     // t = A s, omega
-            k.blas(kOpBiXR, x, p, sv, t, r, rh, kEpiBiRho);        // x, r, rho, beta
-        }
+        runner.run(n, [&](int m) {
+            for (int it = 0; it < m; ++it) {
+                const int *skip = &k.sc->done;
+                k.blas(kOpBiP, r, p, v);                               // p = r + b (p - w v)
+                k.apply(p, v, false, kEpiBiAlpha, rh, skip);           // v = A p, alpha
+                k.blas(kOpBiS, r, v, sv);                              // s = r - alpha v
+                k.apply(sv, t, false, kEpiBiOmega, nullptr, skip);     // t = A s, omega
+                k.blas(kOpBiXR, x, p, sv, t, r, rh, kEpiBiRho);        // x, r, rho, beta
+            }
+        });
         h = read_scalars(k.sc, k.s);
         if (h.rr < 0.99 * best) {
             best = h.rr;
@@ -455,8 +523,27 @@ static Cost iter_cost(const Geom &g, int prec, bool link12, bool eo, bool bicg) 
 
 constexpr int kMaxRestarts = 40;
 
-int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why) {
+// WL_GRAPH solves run on the library's stream once the caller's stream has
+// drained; returns false (and sets why) when that fails.
+static bool graph_setup(SolveIn &in, std::string *why) {
+    if (!(in.flags & WL_GRAPH)) return true;
+    hipError_t e = hipStreamSynchronize(in.s);
+    if (e == hipSuccess) {
+        try {
+            in.s = graph_stream();
+        } catch (const Fail &f) {
+            e = f.err;
+        }
+    }
+    if (e != hipSuccess) *why = std::string("HIP error preparing graph replay: ") + hipGetErrorString(e);
+    return e == hipSuccess;
+}
+
+int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *why) {
     const auto t0 = std::chrono::steady_clock::now();
+    SolveIn in = in0;
+    if (!graph_setup(in, why)) return WL_EHIP;
+    const bool graph = in.flags & WL_GRAPH;
     const Geom &g = in.g;
     const bool eo = in.flags & WL_EO;
     const bool link12 = in.flags & WL_LINK12;
@@ -501,6 +588,7 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
                 const int lo = lo_prec(in.flags);
                 Space k32{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
                           ws.partials, ws.v32[7]};
+                k.graph = k32.graph = graph;
                 if (mixed)
                     check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
                 void *rhs = const_cast<void *>(in.b);
@@ -563,6 +651,7 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
                 const int lo = lo_prec(in.flags);
                 Space k{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
                         ws.partials, ws.v32[7]};
+                k.graph = graph;
                 check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
                 // the precision floor of the inner solve: FP16 storage cannot
                 // reach 1e-5 relative
@@ -676,23 +765,28 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
         return true;
     };
     int done_it = 0;
+    ChunkRunner runner(k.s, k.graph);
     while (!all_done() && done_it < maxit) {
         const int n = std::min(chunk, maxit - done_it);
-        for (int it = 0; it < n; ++it) {
-            const int *skip = &k.sc->done;
-            k.apply(p, t, false, kEpiCgPap, nullptr, skip);
-            k.apply(t, q, true, kEpiNone, nullptr, skip);
-            k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
-            k.blas(kOpCgP, r, p);
-        }
+        runner.run(n, [&](int m) {
+            for (int it = 0; it < m; ++it) {
+                const int *skip = &k.sc->done;
+                k.apply(p, t, false, kEpiCgPap, nullptr, skip);
+                k.apply(t, q, true, kEpiNone, nullptr, skip);
+                k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+                k.blas(kOpCgP, r, p);
+            }
+        });
         done_it += n;
         read_scalars_n(k.sc, k.nrhs, k.s, h);
     }
     for (int i = 0; i < k.nrhs; ++i) iters[i] = h[i].iter;
 }
 
-int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why) {
+int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *why) {
     const auto t0 = std::chrono::steady_clock::now();
+    SolveIn in = in0;
+    if (!graph_setup(in, why)) return WL_EHIP;
     const Geom &g = in.g;
     const bool eo = in.flags & WL_EO;
     const bool link12 = in.flags & WL_LINK12;
@@ -711,6 +805,7 @@ int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *w
     Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, sc, partials, v[7]};
     k.nrhs = nrhs;
     k.fstride = fs;
+    k.graph = in.flags & WL_GRAPH;
 
     std::vector<double> b2(nrhs), r2(nrhs), mb2(nrhs), eta(nrhs, in.tol), targets(nrhs);
     std::vector<int> iters(nrhs, 0), total(nrhs, 0), restarts(nrhs, 0), status(nrhs, WL_NOCONV);

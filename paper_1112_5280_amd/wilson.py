@@ -31,6 +31,7 @@ HOP = 0x10
 EO = 0x20
 MIXED = 0x40
 X0 = 0x80
+GRAPH = 0x100
 
 OK, NOCONV, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 EINVAL, EWORKSPACE, EHIP = -1, -2, -3
