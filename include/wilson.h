@@ -210,6 +210,31 @@ int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
                    double tol, int32_t maxiter, uint32_t flags, void *work,
                    size_t work_bytes, wl_solve_stats *stats, void *stream);
 
+/* One problem of an uneven batch: its own lattice, kappa and gauge field. */
+typedef struct {
+    int32_t dims[4];      /* lattice extents (even, >= 2) */
+    double kappa;         /* hopping parameter of this problem */
+    const void *gauge;    /* packed FP64 gauge field (link format of flags) */
+    const void *b;        /* packed FP64 full source spinor */
+    void *x;              /* packed FP64 full solution (initial guess, WL_X0) */
+} wl_problem;
+
+/* Scratch bytes for solve_cg_problems on these problems (0 on bad dims). */
+size_t wl_problems_workspace_bytes(const wl_problem *p, int32_t n, uint32_t flags);
+
+/* Uneven batch: solve M_i x_i = b_i by CGNR for n independent problems of
+ * any mix of lattice sizes, kappas and gauge fields (paper Sec. 4: inversions
+ * for many configurations). Problems of one size are solved together as one
+ * batched solve (each with its own gauge field and kappa; up to 64 per group),
+ * and the groups run concurrently on library-owned streams. flags as for
+ * solve_cg_batch (FP64; WL_EO, WL_LINK12, WL_X0, WL_GRAPH). The call waits for
+ * `stream` to drain, then blocks until every problem is done; stats (host,
+ * may be NULL) receives n entries in the order of p. Returns WL_OK when every
+ * problem met tol, else a non-OK status of some problem. */
+int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], double tol,
+                      int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                      wl_solve_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -304,6 +304,44 @@ int wilson_dslash_batch(const void *gauge, const void *in, void *out, int32_t nr
     return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_batch");
 }
 
+size_t wl_problems_workspace_bytes(const wl_problem *p, int32_t n, uint32_t flags) {
+    if (!p || n < 1) return 0;
+    return problems_workspace_bytes(p, n, flags);
+}
+
+int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], double tol,
+                      int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                      wl_solve_stats *stats, void *stream) {
+    Phases ph;
+    std::string why;
+    if (!p || n < 1) return fail(WL_EINVAL, "no problems");
+    if (!get_phases(phases, &ph, &why)) return fail(WL_EINVAL, why);
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    if ((flags & WL_PREC_MASK) != WL_F64 || (flags & (WL_MIXED | WL_DAG | WL_HOP)))
+        return fail(WL_EINVAL, "batched solves are FP64 (no WL_MIXED, WL_DAG or WL_HOP)");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WL_EINVAL, "tol must be positive");
+    if (maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
+    if (!work) return fail(WL_EINVAL, "NULL workspace");
+    for (int i = 0; i < n; ++i) {
+        Geom g;
+        if (!make_geom(p[i].dims, &g, &why))
+            return fail(WL_EINVAL, "problem " + std::to_string(i) + ": " + why);
+        if (!p[i].gauge || !p[i].b || !p[i].x)
+            return fail(WL_EINVAL, "problem " + std::to_string(i) + ": NULL buffer");
+        if (p[i].b == p[i].x) return fail(WL_EINVAL, "problem " + std::to_string(i) + ": b == x");
+        if (!std::isfinite(p[i].kappa))
+            return fail(WL_EINVAL, "problem " + std::to_string(i) + ": kappa is not finite");
+    }
+    const size_t need = problems_workspace_bytes(p, n, flags);
+    if (work_bytes < need)
+        return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                       " bytes, got " + std::to_string(work_bytes));
+    const int st = run_problems(p, n, ph, tol, maxiter, flags, work,
+                                static_cast<hipStream_t>(stream), stats, &why);
+    if (st != WL_OK) g_last_error = why.empty() ? "at least one problem missed tol" : why;
+    return st;
+}
+
 int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
                    const int32_t dims[4], double kappa, const double phases[8], double tol,
                    int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,

@@ -490,6 +490,19 @@ hipError_t launch_set_targets(Scalars *sc, const double *targets, int n, hipStre
     return hipGetLastError();
 }
 
+__global__ void set_kappas_kernel(Scalars *sc, Targets k, int n) {
+    const int r = threadIdx.x;
+    if (blockIdx.x == 0 && r < n) sc[r].kappa = k.t[r];
+}
+
+hipError_t launch_set_kappas(Scalars *sc, const double *kappas, int n, hipStream_t s) {
+    if (n < 1 || n > kMaxBatch) return hipErrorInvalidValue;
+    Targets k{};
+    for (int r = 0; r < n; ++r) k.t[r] = kappas[r];
+    hipLaunchKernelGGL(set_kappas_kernel, dim3(1), dim3(kMaxBatch), 0, s, sc, k, n);
+    return hipGetLastError();
+}
+
 __global__ void beta_ratio_kernel(Scalars *sc, double rr_old) {
     if (threadIdx.x == 0 && blockIdx.x == 0) sc->beta = sc->rr / rr_old;
 }

@@ -75,6 +75,10 @@ struct HopArgs {
     R phr[4], phi[4];      // boundary phases
     const int *skip;
     Reduce red;
+    const void *const *gtab;   // per-RHS gauge fields (or null: `gauge` shared)
+    const Scalars *ksc;        // per-RHS kappa (or null: `c` shared)
+    R cmul;
+    int cpow;
 };
 
 template <int MU, int S, typename R>
@@ -164,8 +168,9 @@ __device__ __forceinline__ void times_phase(cpx<R> o[6], R pr, R pi) {
 
 // One hop direction: forward (FWD) or backward, projector sign S.
 template <typename ST, int NCL, int MU, int S, bool FWD>
-__device__ __forceinline__ void hop_dir(const HopArgs<Real<ST>> &a, const void *in_blk, int p,
-                                        int i, int nb, bool wrap, cpx<Real<ST>> acc[12]) {
+__device__ __forceinline__ void hop_dir(const HopArgs<Real<ST>> &a, const void *gauge,
+                                        const void *in_blk, int p, int i, int nb, bool wrap,
+                                        cpx<Real<ST>> acc[12]) {
     using R = Real<ST>;
     cpx<R> psi[12];
     load_spinor<ST>(in_blk, a.g.S, nb, psi);
@@ -174,11 +179,11 @@ __device__ __forceinline__ void hop_dir(const HopArgs<Real<ST>> &a, const void *
     cpx<R> u[9];
     cpx<R> o[6];
     if constexpr (FWD) {
-        load_link<ST, NCL>(a.gauge, a.g, p, MU, i, u);
+        load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
         su3_mul(u, h, o);
         if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
     } else {
-        load_link<ST, NCL>(a.gauge, a.g, 1 - p, MU, nb, u);
+        load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
         su3_dag_mul(u, h, o);
         if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
     }
@@ -197,6 +202,12 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
     const int b = bl / a.nrhs;
     if (rhs_skip(a.skip, rhs)) return;
     const size_t fo = size_t(rhs) * a.fstride;
+    const void *gauge = a.gtab ? a.gtab[rhs] : a.gauge;
+    R c = a.c;
+    if (a.ksc) {
+        const R k = R(a.ksc[rhs].kappa);
+        c = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
+    }
     int pidx, bi;
     if (WL_PAR_INTERLEAVE && a.npar == 2) {
         pidx = b & 1;
@@ -234,29 +245,29 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
         {   // x direction: neighbour checkerboard index changes through x/2
             const int xp = (x + 1 == g.L[0]) ? 0 : x + 1;
             const int xm = (x == 0) ? g.L[0] - 1 : x - 1;
-            hop_dir<ST, NCL, 0, SF, true>(a, in_blk, p, i, i - xh + (xp >> 1), x == g.L[0] - 1, acc);
-            hop_dir<ST, NCL, 0, SB, false>(a, in_blk, p, i, i - xh + (xm >> 1), x == 0, acc);
+            hop_dir<ST, NCL, 0, SF, true>(a, gauge, in_blk, p, i,i - xh + (xp >> 1), x == g.L[0] - 1, acc);
+            hop_dir<ST, NCL, 0, SB, false>(a, gauge, in_blk, p, i,i - xh + (xm >> 1), x == 0, acc);
         }
         {
             const int st = g.Lxh;
             const int span = (g.L[1] - 1) * st;
-            hop_dir<ST, NCL, 1, SF, true>(a, in_blk, p, i, y == g.L[1] - 1 ? i - span : i + st,
+            hop_dir<ST, NCL, 1, SF, true>(a, gauge, in_blk, p, i,y == g.L[1] - 1 ? i - span : i + st,
                                           y == g.L[1] - 1, acc);
-            hop_dir<ST, NCL, 1, SB, false>(a, in_blk, p, i, y == 0 ? i + span : i - st, y == 0, acc);
+            hop_dir<ST, NCL, 1, SB, false>(a, gauge, in_blk, p, i,y == 0 ? i + span : i - st, y == 0, acc);
         }
         {
             const int st = g.Lxh * g.L[1];
             const int span = (g.L[2] - 1) * st;
-            hop_dir<ST, NCL, 2, SF, true>(a, in_blk, p, i, z == g.L[2] - 1 ? i - span : i + st,
+            hop_dir<ST, NCL, 2, SF, true>(a, gauge, in_blk, p, i,z == g.L[2] - 1 ? i - span : i + st,
                                           z == g.L[2] - 1, acc);
-            hop_dir<ST, NCL, 2, SB, false>(a, in_blk, p, i, z == 0 ? i + span : i - st, z == 0, acc);
+            hop_dir<ST, NCL, 2, SB, false>(a, gauge, in_blk, p, i,z == 0 ? i + span : i - st, z == 0, acc);
         }
         {
             const int st = g.Lxh * g.L[1] * g.L[2];
             const int span = (g.L[3] - 1) * st;
-            hop_dir<ST, NCL, 3, SF, true>(a, in_blk, p, i, t == g.L[3] - 1 ? i - span : i + st,
+            hop_dir<ST, NCL, 3, SF, true>(a, gauge, in_blk, p, i,t == g.L[3] - 1 ? i - span : i + st,
                                           t == g.L[3] - 1, acc);
-            hop_dir<ST, NCL, 3, SB, false>(a, in_blk, p, i, t == 0 ? i + span : i - st, t == 0, acc);
+            hop_dir<ST, NCL, 3, SB, false>(a, gauge, in_blk, p, i,t == 0 ? i + span : i - st, t == 0, acc);
         }
 
         cpx<R> o[12];
@@ -264,10 +275,10 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
         if constexpr (XPAY) {
             load_spinor<ST>(static_cast<const char *>(a.xs[p]) + fo, g.S, i, xv);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) o[k] = xv[k] + a.c * acc[k];
+            for (int k = 0; k < 12; ++k) o[k] = xv[k] + c * acc[k];
         } else {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) o[k] = a.c * acc[k];
+            for (int k = 0; k < 12; ++k) o[k] = c * acc[k];
         }
         store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo, g.S, i, o);
 
@@ -357,6 +368,10 @@ static hipError_t launch_storage(const Geom &g, bool link12, const Phases &ph,
     a.skip = call.skip;
     if (call.red) a.red = *call.red;
     else a.red = Reduce{nullptr, nullptr, kEpiNone, nullptr};
+    a.gtab = call.gtab;
+    a.ksc = call.ksc;
+    a.cmul = R(call.cmul);
+    a.cpow = call.cpow;
     const bool xpay = call.xs[call.first_par] != nullptr;
     return link12 ? launch_ncl<ST, 6>(a, call.dag, xpay, red, s)
                   : launch_ncl<ST, 9>(a, call.dag, xpay, red, s);

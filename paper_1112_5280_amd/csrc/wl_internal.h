@@ -248,6 +248,7 @@ struct Scalars {
     double omega[2];    // BiCGStab omega (complex)
     double beta_c[2];   // BiCGStab beta (complex)
     double sums[kMaxSums];   // totals of the last reduction
+    double kappa;       // hopping parameter of this problem (independent problems)
     int done;           // 1 once converged or broken down: kernels become no-ops
     int iter;           // Krylov iterations since the last (re)start
     int status;         // WL_OK or WL_BREAKDOWN
@@ -277,6 +278,12 @@ struct HopCall {
     const Reduce *red;    // null: no reduction
     int nrhs = 1;         // fields of a batch, fstride bytes apart (gauge shared)
     size_t fstride = 0;
+    // independent problems: RHS r uses gauge gtab[r] (device array) and the
+    // coefficient cmul * kappa_r^cpow with kappa_r = ksc[r].kappa
+    const void *const *gtab = nullptr;
+    const struct Scalars *ksc = nullptr;
+    double cmul = 0.0;
+    int cpow = 0;
 };
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s);
@@ -332,6 +339,8 @@ hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s);
 hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s);
 // launch_set_target for RHS 0..n-1 of a batch (n <= kMaxBatch), host targets
 hipError_t launch_set_targets(Scalars *sc, const double *targets, int n, hipStream_t s);
+// sc[r].kappa = kappas[r] for r < n (n <= kMaxBatch), host values
+hipError_t launch_set_kappas(Scalars *sc, const double *kappas, int n, hipStream_t s);
 
 // ---- solvers ---------------------------------------------------------------
 size_t workspace_bytes(const Geom &g, uint32_t flags);
@@ -347,6 +356,11 @@ struct SolveIn {
     uint32_t flags;
     void *work;
     hipStream_t s;
+    // batches of independent problems (one lattice size): per-RHS gauge
+    // fields (device table) and hopping parameters (host array)
+    const void *const *gtab = nullptr;
+    const double *kappas = nullptr;
+    bool own_stream = false;   // `s` belongs to the library: capture on it directly
 };
 
 int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why);
@@ -354,5 +368,11 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
 // batched CG (FP64, full or even-odd): nrhs fields of b and x, st[nrhs]
 size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs);
 int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why);
+
+// independent problems of several lattice sizes, solved concurrently
+size_t problems_workspace_bytes(const wl_problem *p, int n, uint32_t flags);
+int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int maxiter,
+                 uint32_t flags, void *work, hipStream_t caller, wl_solve_stats *st,
+                 std::string *why);
 
 }  // namespace wl

@@ -20,6 +20,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "wl_internal.h"
@@ -88,10 +90,21 @@ static void check(hipError_t e) {
     if (e != hipSuccess) throw Fail{e};
 }
 
+// Per-thread pinned host buffer for status readbacks (kMaxBatch scalar
+// blocks), released when the thread ends.
+struct PinnedScalars {
+    Scalars *p = nullptr;
+    ~PinnedScalars() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
 static Scalars *host_scalars() {
-    thread_local Scalars *h = nullptr;
-    if (!h) check(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Scalars), hipHostMallocDefault));
-    return h;
+    thread_local PinnedScalars buf;
+    if (!buf.p)
+        check(hipHostMalloc(reinterpret_cast<void **>(&buf.p), sizeof(Scalars) * kMaxBatch,
+                            hipHostMallocDefault));
+    return buf.p;
 }
 
 static Scalars read_scalars(const Scalars *dev, hipStream_t s) {
@@ -122,6 +135,22 @@ struct Space {
     int nrhs = 1;
     size_t fstride = 0;
     bool graph = false;      // replay chunks of Krylov iterations from a HIP graph
+    // independent problems: per-RHS gauge fields (device table) and kappa
+    // (sc[r].kappa); the hop coefficient is then cmul * kappa_r^cpow
+    const void *const *gtab = nullptr;
+    bool per_kappa = false;
+
+    // hop coefficient c = cmul * kappa^cpow, for the shared or per-RHS kappa
+    void coef(HopCall &c, double cmul, int cpow) const {
+        c.gtab = gtab;
+        if (per_kappa) {
+            c.ksc = sc;
+            c.cmul = cmul;
+            c.cpow = cpow;
+        } else {
+            c.c = cmul * (cpow == 2 ? kappa * kappa : cpow == 1 ? kappa : 1.0);
+        }
+    }
 
     int npar() const { return eo ? 1 : 2; }
     size_t blk() const { return spinor_block_bytes(*g, prec); }
@@ -144,16 +173,18 @@ struct Space {
             c.xs[0] = in; c.xs[1] = par(in, 1);
             c.aux[0] = aux; c.aux[1] = aux ? par(aux, 1) : nullptr;
             c.out[0] = out; c.out[1] = par(out, 1);
-            c.first_par = 0; c.npar = 2; c.c = -kappa; c.dag = dag; c.skip = skip; c.red = rp;
+            c.first_par = 0; c.npar = 2; c.dag = dag; c.skip = skip; c.red = rp;
             c.nrhs = nrhs; c.fstride = fstride;
+            coef(c, -1.0, 1);
             check(launch_hop(*g, prec, link12, ph, c, s));
         } else {
             HopCall c1{};
             c1.gauge = gauge;
             c1.in[0] = in;
             c1.out[1] = tmp;
-            c1.first_par = 1; c1.npar = 1; c1.c = 1.0; c1.dag = dag; c1.skip = skip;
+            c1.first_par = 1; c1.npar = 1; c1.dag = dag; c1.skip = skip;
             c1.nrhs = nrhs; c1.fstride = fstride;
+            coef(c1, 1.0, 0);
             check(launch_hop(*g, prec, link12, ph, c1, s));
             HopCall c2{};
             c2.gauge = gauge;
@@ -161,9 +192,10 @@ struct Space {
             c2.xs[0] = in;
             c2.aux[0] = aux;
             c2.out[0] = out;
-            c2.first_par = 0; c2.npar = 1; c2.c = -kappa * kappa; c2.dag = dag; c2.skip = skip;
+            c2.first_par = 0; c2.npar = 1; c2.dag = dag; c2.skip = skip;
             c2.red = rp;
             c2.nrhs = nrhs; c2.fstride = fstride;
+            coef(c2, -1.0, 2);
             check(launch_hop(*g, prec, link12, ph, c2, s));
         }
         applies += 1;
@@ -251,10 +283,17 @@ struct ChunkRunner {
 
 // The library's own stream for captured solves (graphs cannot be captured on
 // the null stream); default priority, one per host thread.
+struct OwnedStream {
+    hipStream_t s = nullptr;
+    ~OwnedStream() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
 static hipStream_t graph_stream() {
-    thread_local hipStream_t s = nullptr;
-    if (!s) check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    return s;
+    thread_local OwnedStream os;
+    if (!os.s) check(hipStreamCreateWithFlags(&os.s, hipStreamNonBlocking));
+    return os.s;
 }
 
 constexpr int kStallWindow = 2000;
@@ -459,8 +498,9 @@ static void eo_source(Space &k, const void *b_full, void *bhat_e) {
     c.in[1] = k.par(b_full, 1);
     c.xs[0] = b_full;
     c.out[0] = bhat_e;
-    c.first_par = 0; c.npar = 1; c.c = k.kappa; c.dag = false;
+    c.first_par = 0; c.npar = 1; c.dag = false;
     c.nrhs = k.nrhs; c.fstride = k.fstride;
+    k.coef(c, 1.0, 1);
     check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
 }
 
@@ -471,8 +511,9 @@ static void eo_reconstruct(Space &k, const void *b_full, void *x_full) {
     c.in[0] = x_full;
     c.xs[1] = k.par(b_full, 1);
     c.out[1] = k.par(x_full, 1);
-    c.first_par = 1; c.npar = 1; c.c = k.kappa; c.dag = false;
+    c.first_par = 1; c.npar = 1; c.dag = false;
     c.nrhs = k.nrhs; c.fstride = k.fstride;
+    k.coef(c, 1.0, 1);
     check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
 }
 
@@ -526,7 +567,7 @@ constexpr int kMaxRestarts = 40;
 // WL_GRAPH solves run on the library's stream once the caller's stream has
 // drained; returns false (and sets why) when that fails.
 static bool graph_setup(SolveIn &in, std::string *why) {
-    if (!(in.flags & WL_GRAPH)) return true;
+    if (!(in.flags & WL_GRAPH) || in.own_stream) return true;
     hipError_t e = hipStreamSynchronize(in.s);
     if (e == hipSuccess) {
         try {
@@ -732,9 +773,7 @@ size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs) {
 }
 
 static void read_scalars_n(const Scalars *dev, int n, hipStream_t s, Scalars *out) {
-    thread_local Scalars *h = nullptr;
-    if (!h) check(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Scalars) * kMaxBatch,
-                                hipHostMallocDefault));
+    Scalars *h = host_scalars();
     check(hipMemcpyAsync(h, dev, sizeof(Scalars) * n, hipMemcpyDeviceToHost, s));
     check(hipStreamSynchronize(s));
     std::memcpy(out, h, sizeof(Scalars) * n);
@@ -806,6 +845,8 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     k.nrhs = nrhs;
     k.fstride = fs;
     k.graph = in.flags & WL_GRAPH;
+    full.gtab = k.gtab = in.gtab;
+    full.per_kappa = k.per_kappa = in.kappas != nullptr;
 
     std::vector<double> b2(nrhs), r2(nrhs), mb2(nrhs), eta(nrhs, in.tol), targets(nrhs);
     std::vector<int> iters(nrhs, 0), total(nrhs, 0), restarts(nrhs, 0), status(nrhs, WL_NOCONV);
@@ -826,6 +867,7 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
         bytes += nrhs * (tr.bytes + 3.0 * 2 * g.Vh * 192.0);
     };
     try {
+        if (in.kappas) check(launch_set_kappas(sc, in.kappas, nrhs, in.s));
         if (!(in.flags & WL_X0))
             full.blas(kOpZero, in.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
         norm2_n(full, in.b, b2.data());
@@ -914,6 +956,157 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
         }
         if (status[r] < 0) ret = status[r];
         else if (ret == WL_OK) ret = status[r];
+    }
+    return ret;
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batches of independent problems (lattices of several sizes, each
+// with its own gauge field and kappa). Problems of one size form a group
+// solved as one batched CG (per-RHS gauge table and kappa); the groups run
+// concurrently, each on its own host thread and its own stream, so the GPU
+// overlaps the small lattices. Sources are copied into the group's contiguous
+// batch and solutions copied back.
+// ---------------------------------------------------------------------------
+constexpr size_t kMaxGroupThreads = 8;
+
+struct Group {
+    Geom g;
+    std::vector<int> idx;
+    size_t off, fs;
+};
+
+static std::vector<Group> plan_groups(const wl_problem *p, int n, uint32_t flags, size_t *total,
+                                      std::string *why) {
+    std::vector<Group> gs;
+    size_t off = 0;
+    std::vector<char> used(n, 0);
+    for (int i = 0; i < n; ++i) {
+        if (used[i]) continue;
+        Geom g;
+        if (!make_geom(p[i].dims, &g, why)) return {};
+        std::vector<int> same;
+        for (int j = i; j < n; ++j)
+            if (!used[j] && std::memcmp(p[j].dims, p[i].dims, sizeof(p[i].dims)) == 0) {
+                same.push_back(j);
+                used[j] = 1;
+            }
+        for (size_t a = 0; a < same.size(); a += kMaxBatch) {
+            Group gr;
+            gr.g = g;
+            gr.idx.assign(same.begin() + a, same.begin() + std::min(same.size(), a + kMaxBatch));
+            gr.fs = align_up(2 * spinor_block_bytes(g, WL_F64));
+            gr.off = off;
+            const size_t m = gr.idx.size();
+            off += align_up(m * sizeof(void *)) + 2 * m * gr.fs +
+                   workspace_bytes_batch(g, flags, int(m));
+            gs.push_back(gr);
+        }
+    }
+    *total = off;
+    return gs;
+}
+
+size_t problems_workspace_bytes(const wl_problem *p, int n, uint32_t flags) {
+    size_t total = 0;
+    std::string why;
+    plan_groups(p, n, flags, &total, &why);
+    return total;
+}
+
+int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int maxiter,
+                 uint32_t flags, void *work, hipStream_t caller, wl_solve_stats *st,
+                 std::string *why) {
+    size_t total = 0;
+    std::vector<Group> gs = plan_groups(p, n, flags, &total, why);
+    if (gs.empty()) return WL_EINVAL;
+    if (hipStreamSynchronize(caller) != hipSuccess) {
+        *why = "caller stream failed";
+        return WL_EHIP;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *why = "hipGetDevice failed";
+        return WL_EHIP;
+    }
+    std::vector<int> gstatus(gs.size(), WL_OK);
+    std::vector<std::string> gwhy(gs.size());
+    std::vector<std::vector<wl_solve_stats>> gst(gs.size());
+    auto work_group = [&](size_t gi) {
+        const Group &gr = gs[gi];
+        const int m = int(gr.idx.size());
+        gst[gi].assign(m, wl_solve_stats{});
+        hipStream_t s = nullptr;
+        try {
+            check(hipSetDevice(dev));   // the device is per host thread
+            check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            char *base = static_cast<char *>(work) + gr.off;
+            const void **gtab = reinterpret_cast<const void **>(base);
+            char *bb = base + align_up(m * sizeof(void *));
+            char *xb = bb + m * gr.fs;
+            void *ws = xb + m * gr.fs;
+            std::vector<const void *> ptrs(m);
+            std::vector<double> kap(m);
+            const size_t fbytes = 2 * spinor_block_bytes(gr.g, WL_F64);
+            for (int r = 0; r < m; ++r) {
+                const wl_problem &q = p[gr.idx[r]];
+                ptrs[r] = q.gauge;
+                kap[r] = q.kappa;
+                check(hipMemcpyAsync(bb + r * gr.fs, q.b, fbytes, hipMemcpyDeviceToDevice, s));
+                if (flags & WL_X0)
+                    check(hipMemcpyAsync(xb + r * gr.fs, q.x, fbytes, hipMemcpyDeviceToDevice, s));
+            }
+            check(hipMemcpyAsync(gtab, ptrs.data(), m * sizeof(void *), hipMemcpyHostToDevice, s));
+            check(hipStreamSynchronize(s));
+            SolveIn in{};
+            in.gauge = ptrs[0];
+            in.b = bb;
+            in.x = xb;
+            in.g = gr.g;
+            in.kappa = kap[0];
+            in.ph = ph;
+            in.tol = tol;
+            in.maxiter = maxiter;
+            in.flags = flags;
+            in.work = ws;
+            in.s = s;
+            in.gtab = gtab;
+            in.kappas = kap.data();
+            in.own_stream = true;
+            gstatus[gi] = run_cg_batch(in, m, gst[gi].data(), &gwhy[gi]);
+            for (int r = 0; r < m; ++r)
+                check(hipMemcpyAsync(p[gr.idx[r]].x, xb + r * gr.fs, fbytes,
+                                     hipMemcpyDeviceToDevice, s));
+            check(hipStreamSynchronize(s));
+        } catch (const Fail &f) {
+            if (s) (void)hipStreamSynchronize(s);
+            gstatus[gi] = WL_EHIP;
+            gwhy[gi] = std::string("HIP error in problem batch: ") + hipGetErrorString(f.err);
+        } catch (const std::exception &e) {
+            if (s) (void)hipStreamSynchronize(s);
+            gstatus[gi] = WL_EHIP;
+            gwhy[gi] = std::string("host error in problem batch: ") + e.what();
+        }
+        if (s) (void)hipStreamDestroy(s);
+    };
+    // a small pool of host threads takes the groups in order
+    std::atomic<size_t> next{0};
+    auto worker = [&]() {
+        for (size_t gi; (gi = next.fetch_add(1)) < gs.size();) work_group(gi);
+    };
+    const size_t nthreads = std::min<size_t>(gs.size(), kMaxGroupThreads);
+    std::vector<std::thread> threads;
+    for (size_t t = 1; t < nthreads; ++t) threads.emplace_back(worker);
+    worker();
+    for (auto &t : threads) t.join();
+    int ret = WL_OK;
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+        for (size_t r = 0; r < gs[gi].idx.size(); ++r)
+            if (st) st[gs[gi].idx[r]] = gst[gi][r];
+        if (gstatus[gi] != WL_OK && (ret == WL_OK || gstatus[gi] < 0)) {
+            ret = gstatus[gi];
+            *why = gwhy[gi];
+        }
     }
     return ret;
 }

@@ -44,7 +44,8 @@ ANTIPERIODIC_T = (1.0, 1.0, 1.0, -1.0)
 SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor",
            "wilson_dslash", "wilson_dslash_eo", "wl_workspace_bytes",
-           "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch")
+           "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch",
+           "wl_problems_workspace_bytes", "solve_cg_problems")
 
 
 class WilsonError(RuntimeError):
@@ -94,6 +95,11 @@ def _load():
     lib.solve_cg_batch.argtypes = [P, P, P, I32, P, D, P, D, I32, U32, P, SZ,
                                    ctypes.POINTER(SolveStats), P]
     lib.solve_cg_batch.restype = ctypes.c_int
+    lib.wl_problems_workspace_bytes.argtypes = [P, I32, U32]
+    lib.wl_problems_workspace_bytes.restype = SZ
+    lib.solve_cg_problems.argtypes = [P, I32, P, D, I32, U32, P, SZ,
+                                      ctypes.POINTER(SolveStats), P]
+    lib.solve_cg_problems.restype = ctypes.c_int
     return lib
 
 
@@ -297,11 +303,55 @@ def solve_cg_batch(gauge, b, x, nrhs, dims, kappa, phases=ANTIPERIODIC_T, tol=1e
     return code, out
 
 
+class ProblemDesc(ctypes.Structure):
+    """The C struct wl_problem."""
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("kappa", ctypes.c_double),
+                ("gauge", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
 @dataclass
 class Problem:
-    """A lattice problem resident on the device (packed gauge field)."""
+    """One problem of an uneven batch: packed FP64 gauge field, source and solution
+    (full lattice, packed layout) resident on the device."""
     dims: tuple
     kappa: float
     gauge: torch.Tensor
-    flags: int = F64
-    phases: tuple = ANTIPERIODIC_T
+    b: torch.Tensor
+    x: torch.Tensor
+
+
+def _problem_array(problems):
+    arr = (ProblemDesc * len(problems))()
+    for i, q in enumerate(problems):
+        arr[i].dims = _dims(q.dims)
+        arr[i].kappa = float(q.kappa)
+        arr[i].gauge = q.gauge.data_ptr()
+        arr[i].b = q.b.data_ptr()
+        arr[i].x = q.x.data_ptr()
+    return arr
+
+
+def problems_workspace_bytes(problems, flags=F64):
+    arr = _problem_array(problems)
+    return lib.wl_problems_workspace_bytes(arr, len(problems), flags)
+
+
+def solve_cg_problems(problems, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000, flags=F64,
+                      work=None, stream=None):
+    """CGNR over an uneven batch of independent problems (sizes, kappas and gauge
+    fields may all differ); returns (status, [stats per problem])."""
+    arr = _problem_array(problems)
+    n = len(problems)
+    need = lib.wl_problems_workspace_bytes(arr, n, flags)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=problems[0].b.device)
+    st = (SolveStats * n)()
+    code = lib.solve_cg_problems(arr, n, _phases(phases), float(tol), int(maxiter), flags,
+                                 _ptr(work), work.numel(), st, _stream(stream))
+    _check(code, "solve_cg_problems")
+    out = []
+    for s in st:
+        d = s.as_dict()
+        d["status_name"] = STATUS_NAMES.get(d["status"], "?")
+        out.append(d)
+    return code, out

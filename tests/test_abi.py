@@ -90,3 +90,29 @@ def test_solver_argument_checks(w):
     assert call(flags=w.F32) == -1                # solver buffers are FP64
     assert call(flags=w.DAG) == -1
     assert call(dims=w._dims((4, 4, 4, 5))) == -1
+
+
+def test_problem_argument_checks(w):
+    ph = w._phases(w.ANTIPERIODIC_T)
+    arr = (w.ProblemDesc * 2)()
+    for i, dims in enumerate(((4, 4, 4, 4), (4, 4, 4, 8))):
+        arr[i].dims = w._dims(dims)
+        arr[i].kappa = 0.12
+        arr[i].gauge, arr[i].b, arr[i].x = 8, 16 + 64 * i, 24 + 64 * i
+    st = (w.SolveStats * 2)()
+    need = w.lib.wl_problems_workspace_bytes(arr, 2, 0)
+    # two sizes make two groups
+    assert need > w.lib.wl_problems_workspace_bytes(arr, 1, 0) > 0
+    call = lambda n=2, flags=0, work=need, tol=1e-10: w.lib.solve_cg_problems(
+        arr, n, ph, tol, 10, flags, _p(32), work, st, None)
+    assert call(n=0) == -1
+    assert call(work=need - 1) == -2 and "workspace" in w.last_error()
+    assert call(flags=w.MIXED) == -1
+    assert call(flags=w.F32) == -1
+    assert call(tol=-1.0) == -1
+    arr[1].dims = w._dims((4, 4, 3, 8))
+    assert call() == -1 and "problem 1" in w.last_error()
+    assert w.lib.wl_problems_workspace_bytes(arr, 2, 0) == 0
+    arr[1].dims = w._dims((4, 4, 4, 8))
+    arr[1].x = arr[1].b
+    assert call() == -1 and "b == x" in w.last_error()
