@@ -28,6 +28,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# algorithmic bytes per site of one spinor, and per complex link entry, by
+# storage: FP64, FP32, FP16 (24 halves plus one FP32 scale per spinor)
+SPINOR_BYTES = {0x0: 192, 0x1: 96, 0x2: 52}
+COMPLEX_BYTES = {0x0: 16, 0x1: 8, 0x2: 4}
+
 WORKLOADS = {
     # name: dims, kappa, eps
     "32^3x64": ((32, 32, 32, 64), 0.155, 0.35),
@@ -46,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 12-point-source and 64-lattice batch measurements")
     return ap.parse_args()
 
 
@@ -53,11 +60,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the sources that define the hopping kernels (their code, layout and reductions)
+HOP_SOURCES = ("wl_dslash.hip", "wl_internal.h", "wl_reduce.h")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1112_5280_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in HOP_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,6 +103,130 @@ def time_kernel(fn, n, torch):
         e1.record(s)
     ev[-1][1].synchronize()
     return sum(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3 / n
+
+
+def timed(fn, torch):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def batch12(w, torch, synth, n_launch):
+    """The 12 spin-colour point sources on the 24^3 x 48 lattice (eps = 0.3,
+    kappa = 0.15): batched M GB/s at 432 B per site-RHS (FP64-18), and one
+    batched FP64 eo-CG solve of all 12 against 12 solo solves."""
+    dims, kappa = (24, 24, 24, 48), 0.15
+    V = synth.volume(dims)
+    U = synth.gauge_smooth(dims, 0.30, 0)
+    site = synth.random_site(dims, 2)
+    n = 12
+    out = {"lattice": list(dims), "kappa": kappa, "source_site": site}
+    s = torch.cuda.current_stream()
+    ops = {}
+    for prec, lk, name in ((w.F64, w.LINK18, "f64_18"), (w.F32, w.LINK18, "f32_18"),
+                           (w.F32, w.LINK12, "f32_12")):
+        G = w.pack_gauge(U, dims, prec | lk)
+        B = w.empty_batch(dims, n, prec)
+        for r in range(n):
+            w.batch_field(B, dims, prec, r).copy_(
+                w.pack_spinor(synth.point_source(dims, site, r // 3, r % 3), dims, prec))
+        O = w.empty_batch(dims, n, prec)
+        f = prec | lk
+        tm = time_kernel(lambda: w.wilson_dslash_batch(G, B, O, n, dims, kappa, flags=f,
+                                                       stream=s), n_launch, torch)
+        per = 2 * SPINOR_BYTES[prec] + 4 * COMPLEX_BYTES[prec] * (6 if lk else 9) / n
+        P1 = w.batch_field(B, dims, prec, 0)
+        O1 = w.empty_spinor(dims, prec)
+        t1 = time_kernel(lambda: w.wilson_dslash(G, P1, O1, dims, kappa, flags=f, stream=s),
+                         n_launch, torch)
+        ops["M_batch12_" + name] = {
+            "us": tm * 1e6, "bytes_per_site_rhs": per, "GBs": per * V * n / tm / 1e9,
+            "GFLOPs": 1368.0 * V * n / tm / 1e9, "single_rhs_us": t1 * 1e6,
+            "speedup_vs_12_single": 12 * t1 / tm}
+        del G, B, O, O1
+    out["dslash"] = ops
+    torch.cuda.empty_cache()
+
+    G = w.pack_gauge(U, dims, w.F64)
+    B = w.empty_batch(dims, n)
+    for r in range(n):
+        w.batch_field(B, dims, 0, r).copy_(
+            w.pack_spinor(synth.point_source(dims, site, r // 3, r % 3), dims))
+    X = w.empty_batch(dims, n)
+    solves = {}
+    for f, name in ((w.EO, "batched_f64_eo"), (w.EO | w.GRAPH, "batched_f64_eo_graph")):
+        work = torch.empty(w.workspace_bytes(dims, f, n), dtype=torch.uint8, device="cuda")
+        (code, st), dt = timed(lambda: w.solve_cg_batch(G, B, X, n, dims, kappa, flags=f,
+                                                        work=work, stream=s), torch)
+        assert code == 0 and max(x["true_res"] for x in st) <= 1e-10, st
+        solves[name] = {"seconds": dt, "solves_per_s": n / dt,
+                        "iterations_max": max(x["iterations"] for x in st),
+                        "true_res_max": max(x["true_res"] for x in st)}
+        del work
+    X1 = w.empty_spinor(dims)
+    for f, name in ((w.EO, "sequential_f64_eo"), (w.EO | w.MIXED, "sequential_mixed_f32_eo")):
+        work = torch.empty(w.workspace_bytes(dims, f), dtype=torch.uint8, device="cuda")
+        def run():
+            return [w.solve_cg(G, w.batch_field(B, dims, 0, r), X1, dims, kappa, flags=f,
+                               work=work, stream=s) for r in range(n)]
+        st, dt = timed(run, torch)
+        assert all(x["status"] == 0 and x["true_res"] <= 1e-10 for x in st), st
+        solves[name] = {"seconds": dt, "solves_per_s": n / dt,
+                        "iterations_max": max(x["iterations"] for x in st),
+                        "true_res_max": max(x["true_res"] for x in st)}
+        del work
+    out["solves"] = solves
+    out["batched_vs_sequential_f64"] = (solves["sequential_f64_eo"]["seconds"] /
+                                        solves["batched_f64_eo"]["seconds"])
+    del G, B, X, X1
+    torch.cuda.empty_cache()
+    return out
+
+
+def uneven64(w, torch, synth, np):
+    """64 independent lattices, sizes uniform over {4^4, 8^4, 8^3 x 16}, kappa
+    uniform in [0.10, 0.14] (seed 3), Haar gauge fields and Gaussian sources of
+    their own seeds: one solve_cg_problems call against 64 solo solves."""
+    sizes = ((4, 4, 4, 4), (8, 8, 8, 8), (8, 8, 8, 16))
+    rng = np.random.default_rng(3)
+    probs = []
+    for i in range(64):
+        dims = sizes[rng.integers(3)]
+        kappa = float(rng.uniform(0.10, 0.14))
+        G = w.pack_gauge(synth.gauge_haar(dims, 100 + i), dims)
+        B = w.pack_spinor(synth.gaussian_spinor(dims, 200 + i), dims)
+        probs.append(w.Problem(dims, kappa, G, B, w.zeros_spinor(dims)))
+    s = torch.cuda.current_stream()
+    out = {"lattices": 64, "sites_total": int(sum(synth.volume(p.dims) for p in probs))}
+    for f, name in ((w.EO, "f64_eo"), (w.EO | w.GRAPH, "f64_eo_graph")):
+        work = torch.empty(w.problems_workspace_bytes(probs, f), dtype=torch.uint8,
+                           device="cuda")
+        w.solve_cg_problems(probs, flags=f, work=work, stream=s)      # warm-up
+        (code, st), dt = timed(lambda: w.solve_cg_problems(probs, flags=f, work=work,
+                                                           stream=s), torch)
+        assert code == 0 and max(x["true_res"] for x in st) <= 1e-10
+        out["batched_" + name] = {"seconds": dt, "lattice_solves_per_s": 64 / dt,
+                                  "iterations_max": max(x["iterations"] for x in st)}
+        wk = {}
+        for p in probs:
+            if p.dims not in wk:
+                wk[p.dims] = torch.empty(w.workspace_bytes(p.dims, f), dtype=torch.uint8,
+                                         device="cuda")
+        def run():
+            return [w.solve_cg(p.gauge, p.b, p.x, p.dims, p.kappa, flags=f, work=wk[p.dims],
+                               stream=s) for p in probs]
+        run()
+        st, dt = timed(run, torch)
+        assert all(x["status"] == 0 for x in st)
+        out["sequential_" + name] = {"seconds": dt, "lattice_solves_per_s": 64 / dt}
+        del work, wk
+    out["batched_vs_sequential"] = (out["sequential_f64_eo"]["seconds"] /
+                                    out["batched_f64_eo"]["seconds"])
+    out["batched_graph_vs_sequential"] = (out["sequential_f64_eo"]["seconds"] /
+                                          out["batched_f64_eo_graph"]["seconds"])
+    return out
 
 
 def main():
@@ -169,17 +304,36 @@ def main():
                 "mixed_vs_fp64_solution_rel_diff": diff}
         del X64, w64, x64
 
+    # the same solve with FP16-storage (per-site scaled) inner iterations
+    f16 = None
+    if not args.no_fp64_compare:
+        f16f = w.EO | w.MIXED | w.F16S | link
+        wk = torch.empty(w.workspace_bytes(dims, f16f), dtype=torch.uint8, device="cuda")
+        X16 = w.empty_spinor(dims)
+        w.solve_cg(G64, B, X16, dims, kappa, tol=1e-10, maxiter=200000, flags=f16f, work=wk,
+                   stream=s)
+        st16, dt = timed(lambda: w.solve_cg(G64, B, X16, dims, kappa, tol=1e-10,
+                                            maxiter=200000, flags=f16f, work=wk, stream=s),
+                         torch)
+        x16 = w.unpack_spinor(X16, dims)
+        f16 = {"seconds": dt, "iterations": st16["iterations"], "status": st16["status_name"],
+               "outer_corrections": st16["restarts"], "true_res": st16["true_res"],
+               "vs_fp32_inner": (ms / 1e3) / dt,
+               "solution_rel_diff_vs_fp32_inner": float(
+                   torch.linalg.vector_norm(x16 - x_dev) / torch.linalg.vector_norm(x_dev))}
+        del wk, X16, x16
+
     # Dslash variants, each timed over a run of launches (HIP events)
     variants = {}
     n = args.kernel_launches
-    for prec, pname in ((w.F64, "f64"), (w.F32, "f32")):
+    for prec, pname in ((w.F64, "f64"), (w.F32, "f32"), (w.F16S, "f16s")):
         for lk, lname in ((w.LINK18, "18"), (w.LINK12, "12")):
             G = w.pack_gauge(U, dims, prec | lk)
             P = w.pack_spinor(b, dims, prec)
             O = w.empty_spinor(dims, prec)
             Oh = w.empty_spinor(dims, prec, 1)
-            sb = 192 if prec == w.F64 else 96
-            lb = (16 if prec == w.F64 else 8) * (6 if lk else 9)
+            sb = SPINOR_BYTES[prec]
+            lb = COMPLEX_BYTES[prec] * (6 if lk else 9)
             f = prec | lk
             tm = time_kernel(lambda: w.wilson_dslash(G, P, O, dims, kappa, flags=f, stream=s),
                              n, torch)
@@ -216,6 +370,15 @@ def main():
                           % (6 if args.link12 else 9),
                 "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
                 "frac_of_copy": ach / copy["GBs"]}
+
+    batch = uneven = None
+    if not args.no_batch:
+        del G64, B, X, work
+        torch.cuda.empty_cache()
+        t = time.time()
+        batch = batch12(w, torch, synth, args.kernel_launches)
+        uneven = uneven64(w, torch, synth, np)
+        log("batch measurements in %.1f s" % (time.time() - t))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -259,10 +422,13 @@ def main():
         "outer_corrections": int(np.mean([st["restarts"] for st in stats])),
         "true_res": max(st["true_res"] for st in stats),
         "fp64_solve": fp64,
+        "mixed_f16_solve": f16,
         "dslash_variants": variants,
         "device_copy": copy,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch12_point_sources": batch,
+        "uneven64_lattices": uneven,
     }
     print(json.dumps(out))
     return 0
