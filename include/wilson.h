@@ -235,6 +235,70 @@ int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], do
                       int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a solve server that admits requests as device memory and solve
+ * slots free up, and runs the admitted solves concurrently (paper Sec. 4: many
+ * inversions per gauge configuration, here served as a request stream).
+ *
+ * The server owns one device arena of `hbm_budget` bytes, taken at creation,
+ * from which each admitted request's solver workspace (wl_workspace_bytes of
+ * its lattice and the server's flags) is carved; gauge fields, sources and
+ * solutions stay caller-owned device memory (gauge fields are typically kept
+ * resident and shared by many requests) and must stay valid until the request
+ * is collected. Requests are admitted first-in first-out: the oldest waiting
+ * request starts as soon as a slot is idle and its workspace fits in the free
+ * arena; each slot is a host thread with its own stream, so the solves of all
+ * admitted requests overlap on the device. A request's result does not depend
+ * on what else is running (every reduction has a fixed order).
+ * ------------------------------------------------------------------------- */
+typedef struct wl_server wl_server;   /* opaque */
+
+typedef struct {
+    size_t hbm_budget;    /* arena bytes for request workspaces (> 0)           */
+    int32_t slots;        /* concurrent solves, 1..64                           */
+    uint32_t flags;       /* solve_cg flags of every request (WL_EO, WL_MIXED,  */
+                          /* WL_F32 / WL_F16S, WL_LINK12, WL_X0, WL_GRAPH)      */
+    double tol;           /* relative true-residual target                       */
+    int32_t maxiter;      /* iteration limit per request                         */
+    double phases[8];     /* boundary phases, as for wilson_dslash               */
+} wl_server_config;
+
+/* Timestamps of one request, seconds since the server was created. */
+typedef struct {
+    double submitted;     /* wl_server_submit returned                          */
+    double admitted;      /* a slot and its workspace were taken                 */
+    double finished;      /* the solution is in x and the slot is free           */
+} wl_request_times;
+
+/* Create a server on the current device. Returns WL_OK and sets *out, or
+ * WL_EINVAL (bad config), WL_EHIP (the arena could not be allocated). */
+int wl_server_create(const wl_server_config *cfg, wl_server **out);
+
+/* Queue a solve of M x = b for one problem (dims, kappa, packed FP64 gauge,
+ * b and x as in wl_problem). Non-blocking; *ticket identifies the request.
+ * WL_EINVAL for a bad problem, WL_EWORKSPACE when its workspace exceeds the
+ * whole arena (it could never be admitted). */
+int wl_server_submit(wl_server *srv, const wl_problem *p, uint64_t *ticket);
+
+/* Block until request `ticket` finishes, collect it and return its solver
+ * status (WL_OK when it met tol); stats and times may be NULL. WL_EINVAL for
+ * an unknown or already collected ticket. */
+int wl_server_wait(wl_server *srv, uint64_t ticket, wl_solve_stats *stats,
+                   wl_request_times *times);
+
+/* Block until any uncollected request finishes (oldest finished first),
+ * collect it, set *ticket and return its status. WL_EINVAL when no request is
+ * pending. */
+int wl_server_next(wl_server *srv, uint64_t *ticket, wl_solve_stats *stats,
+                   wl_request_times *times);
+
+/* Requests submitted but not yet collected (queued, running or finished). */
+int32_t wl_server_pending(wl_server *srv);
+
+/* Finish every queued and running request, then release the slots, streams
+ * and arena. Uncollected results are dropped (solutions are still in x). */
+int wl_server_destroy(wl_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

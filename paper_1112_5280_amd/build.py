@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwilson.so")
 
-SOURCES = ["wl_api.hip", "wl_dslash.hip", "wl_blas.hip", "wl_solver.hip"]
+SOURCES = ["wl_api.hip", "wl_dslash.hip", "wl_blas.hip", "wl_solver.hip", "wl_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = [

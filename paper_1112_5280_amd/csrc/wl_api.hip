@@ -441,4 +441,69 @@ int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims
                         work_bytes, stats, stream);
 }
 
+int wl_server_create(const wl_server_config *cfg, wl_server **out) {
+    std::string why;
+    Phases ph;
+    if (!cfg || !out) return fail(WL_EINVAL, "NULL config or output");
+    *out = nullptr;
+    if (cfg->hbm_budget == 0) return fail(WL_EINVAL, "hbm_budget must be positive");
+    if (cfg->slots < 1 || cfg->slots > 64) return fail(WL_EINVAL, "slots must be in 1..64");
+    if (!get_phases(cfg->phases, &ph, &why)) return fail(WL_EINVAL, why);
+    const uint32_t flags = cfg->flags;
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    const uint32_t inner = flags & WL_PREC_MASK;
+    if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
+        return fail(WL_EINVAL, "a lower precision (WL_F32, WL_F16S) selects the inner solve of "
+                               "WL_MIXED");
+    if (flags & (WL_DAG | WL_HOP)) return fail(WL_EINVAL, "WL_DAG / WL_HOP do not apply to solves");
+    if (!(cfg->tol > 0.0) || !std::isfinite(cfg->tol)) return fail(WL_EINVAL, "tol must be positive");
+    if (cfg->maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
+    const int st = server_create(*cfg, ph, out, &why);
+    return st == WL_OK ? WL_OK : fail(st, why);
+}
+
+int wl_server_submit(wl_server *srv, const wl_problem *p, uint64_t *ticket) {
+    std::string why;
+    Geom g;
+    if (!srv || !p || !ticket) return fail(WL_EINVAL, "NULL server, problem or ticket");
+    if (!make_geom(p->dims, &g, &why)) return fail(WL_EINVAL, why);
+    if (!p->gauge || !p->b || !p->x) return fail(WL_EINVAL, "NULL buffer");
+    if (p->b == p->x) return fail(WL_EINVAL, "b and x alias");
+    if (!std::isfinite(p->kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    const int st = server_submit(srv, *p, g, ticket, &why);
+    return st == WL_OK ? WL_OK : fail(st, why);
+}
+
+static int server_status(int st, const std::string &why) {
+    if (st == WL_OK) return WL_OK;
+    if (st < 0) return fail(st, why);
+    static const char *names[] = {"ok", "not converged within maxiter",
+                                  "breakdown (a Krylov scalar vanished or is not finite)",
+                                  "stagnated"};
+    g_last_error = st > 0 && st < 4 ? names[st] : "error";
+    return st;
+}
+
+int wl_server_wait(wl_server *srv, uint64_t ticket, wl_solve_stats *stats,
+                   wl_request_times *times) {
+    std::string why;
+    if (!srv) return fail(WL_EINVAL, "NULL server");
+    return server_status(server_wait(srv, ticket, stats, times, &why), why);
+}
+
+int wl_server_next(wl_server *srv, uint64_t *ticket, wl_solve_stats *stats,
+                   wl_request_times *times) {
+    std::string why;
+    if (!srv || !ticket) return fail(WL_EINVAL, "NULL server or ticket");
+    return server_status(server_next(srv, ticket, stats, times, &why), why);
+}
+
+int32_t wl_server_pending(wl_server *srv) { return srv ? server_pending(srv) : 0; }
+
+int wl_server_destroy(wl_server *srv) {
+    if (!srv) return WL_OK;
+    const int st = server_destroy(srv);
+    return st == WL_OK ? WL_OK : fail(st, "HIP error releasing the server");
+}
+
 }  // extern "C"

@@ -375,4 +375,15 @@ int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int m
                  uint32_t flags, void *work, hipStream_t caller, wl_solve_stats *st,
                  std::string *why);
 
+// the solve server (wl_server.hip); wl_server itself is the opaque C type
+int server_create(const wl_server_config &cfg, const Phases &ph, wl_server **out, std::string *why);
+int server_submit(wl_server *s, const wl_problem &p, const Geom &g, uint64_t *ticket,
+                  std::string *why);
+int server_wait(wl_server *s, uint64_t ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why);
+int server_next(wl_server *s, uint64_t *ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why);
+int server_pending(wl_server *s);
+int server_destroy(wl_server *s);
+
 }  // namespace wl

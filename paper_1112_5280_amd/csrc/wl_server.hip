@@ -1,0 +1,303 @@
+// wl_server.hip -- the solve server behind wl_server_* (include/wilson.h).
+//
+// Requests (one lattice problem each) wait in a FIFO. A fixed set of slots,
+// each a host thread with its own non-blocking stream, takes the oldest
+// request as soon as the slot is idle and the request's solver workspace fits
+// in the free part of the server's device arena; the solve then runs on the
+// slot's stream, overlapping on the device with every other admitted solve.
+// When it finishes, its workspace returns to the arena and the next request
+// is admitted. The arena is one device allocation made at creation and
+// carved by a first-fit allocator with coalescing, so admission by memory is
+// exact and nothing is allocated per request.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace wl {
+namespace {
+
+constexpr size_t kArenaAlign = 256;
+
+// First-fit allocator over [0, size) with free-block coalescing.
+class Arena {
+  public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+    }
+    size_t size() const { return size_; }
+    bool can_alloc(size_t n) const {
+        for (const auto &f : free_)
+            if (f.second >= n) return true;
+        return false;
+    }
+    bool alloc(size_t n, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n;
+            const size_t at = it->first + n;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        auto it = free_.emplace(off, n).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t size_ = 0;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    wl_problem p{};
+    Geom g{};
+    size_t ws_bytes = 0, ws_off = 0;
+    wl_request_times t{};
+    wl_solve_stats st{};
+    int status = WL_NOCONV;
+    bool done = false;
+    bool claimed = false;   // a wl_server_wait holds it
+};
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace wl
+
+using namespace wl;
+
+struct wl_server {
+    wl_server_config cfg{};
+    Phases ph{};
+    int dev = 0;
+    void *arena_mem = nullptr;
+    Arena arena;
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> slots;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    std::mutex m;
+    std::condition_variable cv_admit, cv_done;
+    std::deque<Request *> queue;                       // waiting, oldest first
+    std::unordered_map<uint64_t, Request *> live;      // every uncollected request
+    std::deque<Request *> finished;                    // finished, not collected
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+
+    bool head_fits() const { return !queue.empty() && arena.can_alloc(queue.front()->ws_bytes); }
+
+    void slot_loop(int k) {
+        const hipError_t e = hipSetDevice(dev);
+        std::unique_lock<std::mutex> lk(m);
+        for (;;) {
+            cv_admit.wait(lk, [&] { return head_fits() || (stopping && queue.empty()); });
+            if (queue.empty()) break;   // stopping and drained
+            Request *r = queue.front();
+            size_t off = 0;
+            if (!arena.alloc(r->ws_bytes, &off)) continue;
+            queue.pop_front();
+            r->ws_off = off;
+            r->t.admitted = seconds_since(t0);
+            if (head_fits()) cv_admit.notify_one();   // the next one may start too
+            lk.unlock();
+
+            std::string why;
+            if (e != hipSuccess) {
+                r->status = WL_EHIP;
+                r->st = wl_solve_stats{};
+                r->st.status = WL_EHIP;
+            } else {
+                SolveIn in{};
+                in.gauge = r->p.gauge;
+                in.b = r->p.b;
+                in.x = r->p.x;
+                in.g = r->g;
+                in.kappa = r->p.kappa;
+                in.ph = ph;
+                in.tol = cfg.tol;
+                in.maxiter = cfg.maxiter;
+                in.flags = cfg.flags;
+                in.work = static_cast<char *>(arena_mem) + off;
+                in.s = streams[k];
+                in.own_stream = true;
+                r->status = run_solver(false, in, &r->st, &why);
+            }
+
+            lk.lock();
+            arena.release(r->ws_off, r->ws_bytes);
+            r->t.finished = seconds_since(t0);
+            r->done = true;
+            finished.push_back(r);
+            cv_done.notify_all();
+            cv_admit.notify_all();
+        }
+    }
+
+    static void collect(Request *r, wl_solve_stats *st, wl_request_times *t) {
+        if (st) *st = r->st;
+        if (t) *t = r->t;
+    }
+
+    // remove a finished request from the bookkeeping (lock held)
+    void forget(Request *r) {
+        for (auto it = finished.begin(); it != finished.end(); ++it)
+            if (*it == r) {
+                finished.erase(it);
+                break;
+            }
+        live.erase(r->ticket);
+        delete r;
+    }
+};
+
+namespace wl {
+
+int server_create(const wl_server_config &cfg, const Phases &ph, wl_server **out,
+                  std::string *why) {
+    auto *s = new wl_server;
+    s->cfg = cfg;
+    s->ph = ph;
+    hipError_t e = hipGetDevice(&s->dev);
+    if (e == hipSuccess) e = hipMalloc(&s->arena_mem, cfg.hbm_budget);
+    for (int k = 0; e == hipSuccess && k < cfg.slots; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) s->streams.push_back(st);
+    }
+    if (e != hipSuccess) {
+        *why = std::string("server setup: ") + hipGetErrorString(e);
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        if (s->arena_mem) (void)hipFree(s->arena_mem);
+        delete s;
+        return WL_EHIP;
+    }
+    s->arena.reset(cfg.hbm_budget / kArenaAlign * kArenaAlign);
+    for (int k = 0; k < cfg.slots; ++k) s->slots.emplace_back(&wl_server::slot_loop, s, k);
+    *out = s;
+    return WL_OK;
+}
+
+int server_submit(wl_server *s, const wl_problem &p, const Geom &g, uint64_t *ticket,
+                  std::string *why) {
+    const size_t need = (workspace_bytes(g, s->cfg.flags) + kArenaAlign - 1) / kArenaAlign *
+                        kArenaAlign;
+    if (need > s->arena.size()) {
+        *why = "request workspace (" + std::to_string(need) + " bytes) exceeds the server's "
+               "HBM budget (" + std::to_string(s->arena.size()) + " bytes)";
+        return WL_EWORKSPACE;
+    }
+    auto *r = new Request;
+    r->p = p;
+    r->g = g;
+    r->ws_bytes = need;
+    std::lock_guard<std::mutex> lk(s->m);
+    if (s->stopping) {
+        delete r;
+        *why = "server is shutting down";
+        return WL_EINVAL;
+    }
+    r->ticket = s->next_ticket++;
+    r->t.submitted = seconds_since(s->t0);
+    s->live[r->ticket] = r;
+    s->queue.push_back(r);
+    *ticket = r->ticket;
+    s->cv_admit.notify_one();
+    return WL_OK;
+}
+
+int server_wait(wl_server *s, uint64_t ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why) {
+    std::unique_lock<std::mutex> lk(s->m);
+    auto it = s->live.find(ticket);
+    if (it == s->live.end() || it->second->claimed) {
+        *why = "unknown or already collected ticket " + std::to_string(ticket);
+        return WL_EINVAL;
+    }
+    Request *r = it->second;
+    r->claimed = true;
+    s->cv_done.wait(lk, [&] { return r->done; });
+    wl_server::collect(r, st, t);
+    const int status = r->status;
+    s->forget(r);
+    return status;
+}
+
+int server_next(wl_server *s, uint64_t *ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why) {
+    std::unique_lock<std::mutex> lk(s->m);
+    auto pick = [&]() -> Request * {
+        for (Request *r : s->finished)
+            if (!r->claimed) return r;
+        return nullptr;
+    };
+    auto unclaimed = [&] {
+        for (const auto &kv : s->live)
+            if (!kv.second->claimed) return true;
+        return false;
+    };
+    if (!unclaimed()) {
+        *why = "no request is pending";
+        return WL_EINVAL;
+    }
+    Request *r = nullptr;
+    s->cv_done.wait(lk, [&] { return (r = pick()) != nullptr || !unclaimed(); });
+    if (!r) {
+        *why = "no request is pending";
+        return WL_EINVAL;
+    }
+    *ticket = r->ticket;
+    wl_server::collect(r, st, t);
+    const int status = r->status;
+    s->forget(r);
+    return status;
+}
+
+int server_pending(wl_server *s) {
+    std::lock_guard<std::mutex> lk(s->m);
+    return int(s->live.size());
+}
+
+int server_destroy(wl_server *s) {
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        s->stopping = true;
+    }
+    s->cv_admit.notify_all();
+    for (auto &th : s->slots) th.join();
+    int ret = WL_OK;
+    for (hipStream_t st : s->streams)
+        if (hipStreamDestroy(st) != hipSuccess) ret = WL_EHIP;
+    if (hipFree(s->arena_mem) != hipSuccess) ret = WL_EHIP;
+    for (auto &kv : s->live) delete kv.second;
+    delete s;
+    return ret;
+}
+
+}  // namespace wl

@@ -45,7 +45,9 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_pack_gauge", "wl_pack_spinor", "wl_unpack_spinor",
            "wilson_dslash", "wilson_dslash_eo", "wl_workspace_bytes",
            "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch",
-           "wl_problems_workspace_bytes", "solve_cg_problems")
+           "wl_problems_workspace_bytes", "solve_cg_problems",
+           "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
+           "wl_server_pending", "wl_server_destroy")
 
 
 class WilsonError(RuntimeError):
@@ -59,6 +61,22 @@ class SolveStats(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    """The C struct wl_server_config."""
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("tol", ctypes.c_double),
+                ("maxiter", ctypes.c_int32), ("phases", ctypes.c_double * 8)]
+
+
+class RequestTimes(ctypes.Structure):
+    """The C struct wl_request_times (seconds since the server was created)."""
+    _fields_ = [("submitted", ctypes.c_double), ("admitted", ctypes.c_double),
+                ("finished", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +118,20 @@ def _load():
     lib.solve_cg_problems.argtypes = [P, I32, P, D, I32, U32, P, SZ,
                                       ctypes.POINTER(SolveStats), P]
     lib.solve_cg_problems.restype = ctypes.c_int
+    lib.wl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(P)]
+    lib.wl_server_create.restype = ctypes.c_int
+    lib.wl_server_submit.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.wl_server_submit.restype = ctypes.c_int
+    lib.wl_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(SolveStats),
+                                   ctypes.POINTER(RequestTimes)]
+    lib.wl_server_wait.restype = ctypes.c_int
+    lib.wl_server_next.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(SolveStats),
+                                   ctypes.POINTER(RequestTimes)]
+    lib.wl_server_next.restype = ctypes.c_int
+    lib.wl_server_pending.argtypes = [P]
+    lib.wl_server_pending.restype = I32
+    lib.wl_server_destroy.argtypes = [P]
+    lib.wl_server_destroy.restype = ctypes.c_int
     return lib
 
 
@@ -355,3 +387,82 @@ def solve_cg_problems(problems, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000
         d["status_name"] = STATUS_NAMES.get(d["status"], "?")
         out.append(d)
     return code, out
+
+
+class Server:
+    """A solve server (wl_server_*): requests of any lattice size are admitted
+    first-in first-out as solve slots and HBM-budget memory free up, and the
+    admitted solves run concurrently, one stream per slot.
+
+    The caller keeps each request's gauge, b and x tensors alive until the
+    request is collected with wait() or next()."""
+
+    def __init__(self, hbm_budget, slots=4, flags=EO | MIXED, tol=1e-10, maxiter=100000,
+                 phases=ANTIPERIODIC_T):
+        cfg = ServerConfig()
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.slots = int(slots)
+        cfg.flags = int(flags)
+        cfg.tol = float(tol)
+        cfg.maxiter = int(maxiter)
+        cfg.phases = _phases(phases)
+        h = ctypes.c_void_p()
+        _check(lib.wl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "wl_server_create")
+        self._h = h
+        self.flags = flags
+        self._keep = {}
+
+    def submit(self, problem):
+        """Queue one Problem (its x receives the solution); returns the ticket."""
+        d = ProblemDesc()
+        d.dims = _dims(problem.dims)
+        d.kappa = float(problem.kappa)
+        d.gauge = problem.gauge.data_ptr()
+        d.b = problem.b.data_ptr()
+        d.x = problem.x.data_ptr()
+        t = ctypes.c_uint64()
+        _check(lib.wl_server_submit(self._h, ctypes.byref(d), ctypes.byref(t)), "wl_server_submit")
+        self._keep[t.value] = problem
+        return t.value
+
+    def _result(self, code, ticket, st, tm):
+        _check(code, "wl_server")
+        self._keep.pop(ticket, None)
+        d = st.as_dict()
+        d["status_name"] = STATUS_NAMES.get(d["status"], "?")
+        return code, d, tm.as_dict()
+
+    def wait(self, ticket):
+        """Block until `ticket` finishes; returns (status, stats, times)."""
+        st, tm = SolveStats(), RequestTimes()
+        code = lib.wl_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(tm))
+        return self._result(code, ticket, st, tm)
+
+    def next(self):
+        """Block until any uncollected request finishes; returns
+        (ticket, status, stats, times)."""
+        st, tm, t = SolveStats(), RequestTimes(), ctypes.c_uint64()
+        code = lib.wl_server_next(self._h, ctypes.byref(t), ctypes.byref(st), ctypes.byref(tm))
+        return (t.value,) + self._result(code, t.value, st, tm)
+
+    def pending(self):
+        return lib.wl_server_pending(self._h)
+
+    def close(self):
+        if self._h is not None:
+            code = lib.wl_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            _check(code, "wl_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

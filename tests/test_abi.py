@@ -116,3 +116,34 @@ def test_problem_argument_checks(w):
     arr[1].dims = w._dims((4, 4, 4, 8))
     arr[1].x = arr[1].b
     assert call() == -1 and "b == x" in w.last_error()
+
+
+def test_server_config_checks(w):
+    """Every config error is caught before the server touches the device."""
+    def cfg(**k):
+        c = w.ServerConfig()
+        c.hbm_budget = k.get("budget", 1 << 30)
+        c.slots = k.get("slots", 4)
+        c.flags = k.get("flags", w.EO | w.MIXED)
+        c.tol = k.get("tol", 1e-10)
+        c.maxiter = k.get("maxiter", 1000)
+        c.phases = w._phases(k.get("phases", w.ANTIPERIODIC_T))
+        return c
+    h = ctypes.c_void_p()
+    create = lambda **k: w.lib.wl_server_create(ctypes.byref(cfg(**k)), ctypes.byref(h))
+    assert create(budget=0) == -1 and "budget" in w.last_error()
+    assert create(slots=0) == -1 and create(slots=65) == -1
+    assert create(flags=w.F32) == -1                 # low precision without WL_MIXED
+    assert create(flags=w.DAG) == -1
+    assert create(tol=0.0) == -1
+    assert create(maxiter=0) == -1
+    assert create(phases=(1, 1, 1, 2)) == -1
+    assert w.lib.wl_server_create(None, ctypes.byref(h)) == -1
+    assert h.value is None
+    # calls on no server fail cleanly
+    t = ctypes.c_uint64()
+    assert w.lib.wl_server_submit(None, None, ctypes.byref(t)) == -1
+    assert w.lib.wl_server_wait(None, 1, None, None) == -1
+    assert w.lib.wl_server_next(None, ctypes.byref(t), None, None) == -1
+    assert w.lib.wl_server_pending(None) == 0
+    assert w.lib.wl_server_destroy(None) == 0

@@ -1,0 +1,120 @@
+"""The solve server: requests of mixed lattice sizes and kappas against
+resident gauge fields, admitted by slots and HBM budget, solved concurrently.
+
+Each served result must equal the same problem solved alone bitwise (every
+reduction has a fixed order, so concurrent work on other streams cannot change
+it), and must meet the FP64 residual bound recomputed by the CPU oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_5280_amd import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+SIZES = ((4, 4, 4, 8), (8, 8, 8, 8), (8, 8, 8, 16), (16, 16, 16, 16))
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_1112_5280_amd import wilson
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return wilson
+
+
+@pytest.fixture(scope="module")
+def fields(w):
+    """One resident exp(i 0.3 H) field per size (canonical copy kept for the oracle)."""
+    out = {}
+    for i, dims in enumerate(SIZES):
+        U = synth.gauge_smooth(dims, 0.3, 40 + i)
+        out[dims] = (U, w.pack_gauge(U, dims), w.pack_gauge(U, dims, w.LINK12))
+    return out
+
+
+def requests(w, fields, n, seed, link12=False):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        dims = SIZES[rng.integers(len(SIZES))]
+        kappa = float(rng.uniform(0.12, 0.155))
+        b = synth.gaussian_spinor(dims, 900 + i)
+        U, G18, G12 = fields[dims]
+        out.append((U, b, w.Problem(dims, kappa, G12 if link12 else G18, w.pack_spinor(b, dims),
+                                    w.zeros_spinor(dims))))
+    return out
+
+
+@pytest.mark.parametrize("flags", [0x20 | 0x40, 0x20 | 0x40 | 0x2, 0x20 | 0x40 | 0x100 | 0x4,
+                                   0x20],
+                         ids=["mixed-f32", "mixed-f16", "mixed-f32-graph-link12", "f64"])
+def test_served_results_equal_solo_solves(w, fields, flags):
+    reqs = requests(w, fields, 24, seed=5, link12=bool(flags & 0x4))
+    with w.Server(hbm_budget=8 << 30, slots=4, flags=flags) as srv:
+        tickets = {srv.submit(p): i for i, (_, _, p) in enumerate(reqs)}
+        got = {}
+        while srv.pending():
+            t, code, st, tm = srv.next()
+            got[tickets[t]] = (code, st, tm)
+    assert sorted(got) == list(range(len(reqs)))
+    overlap = 0
+    ends = sorted((tm["admitted"], tm["finished"]) for _, _, tm in got.values())
+    for (a0, f0), (a1, f1) in zip(ends, ends[1:]):
+        overlap += a1 < f0
+    assert overlap > 0, "no two solves overlapped"
+    one = {}
+    for i, (U, b, p) in enumerate(reqs):
+        code, st, tm = got[i]
+        assert code == 0 and st["status"] == 0, (i, st)
+        assert tm["submitted"] <= tm["admitted"] <= tm["finished"]
+        x = gu.to_np(w.unpack_spinor(p.x, p.dims))
+        res = oracle.true_residual(U, b, x, p.dims, p.kappa)
+        assert res <= 1e-10, (i, p.dims, p.kappa, res)
+        if p.dims not in one:
+            one[p.dims] = w.empty_spinor(p.dims)
+        alone = w.solve_cg(p.gauge, p.b, one[p.dims], p.dims, p.kappa, flags=flags)
+        assert alone["iterations"] == st["iterations"], (i, alone, st)
+        assert np.array_equal(gu.to_np(w.unpack_spinor(one[p.dims], p.dims)), x), i
+
+
+def test_admission_by_hbm_budget(w, fields):
+    """With room for one workspace only, the solves run one after another."""
+    dims = (16, 16, 16, 16)
+    flags = 0x20 | 0x40
+    need = w.workspace_bytes(dims, flags)
+    U, G, _ = fields[dims]
+    ps = [w.Problem(dims, 0.13 + 0.005 * i, G, w.pack_spinor(synth.gaussian_spinor(dims, i), dims),
+                    w.zeros_spinor(dims)) for i in range(4)]
+    with w.Server(hbm_budget=need + 4096, slots=4, flags=flags) as srv:
+        ts = [srv.submit(p) for p in ps]
+        res = [srv.wait(t) for t in ts]
+    spans = [(tm["admitted"], tm["finished"]) for _, _, tm in res]
+    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
+        assert a1 >= f0, spans                  # FIFO, and never two at once
+    for (code, st, _), p in zip(res, ps):
+        assert code == 0
+
+
+def test_server_errors_and_drain(w, fields):
+    dims = (8, 8, 8, 8)
+    U, G, _ = fields[dims]
+    flags = 0x20 | 0x40
+    big = (16, 16, 16, 16)
+    srv = w.Server(hbm_budget=w.workspace_bytes(dims, flags) + 4096, slots=2, flags=flags)
+    with pytest.raises(w.WilsonError):          # could never be admitted
+        srv.submit(w.Problem(big, 0.13, fields[big][1], w.zeros_spinor(big), w.zeros_spinor(big)))
+    with pytest.raises(w.WilsonError):
+        srv.wait(12345)
+    with pytest.raises(w.WilsonError):
+        srv.next()                              # nothing pending
+    srcs = [synth.gaussian_spinor(dims, 70 + i) for i in range(5)]
+    ps = [w.Problem(dims, 0.14, G, w.pack_spinor(s, dims), w.zeros_spinor(dims)) for s in srcs]
+    for p in ps:
+        srv.submit(p)
+    srv.close()                                 # finishes the queue before releasing
+    for s, p in zip(srcs, ps):
+        x = gu.to_np(w.unpack_spinor(p.x, dims))
+        assert oracle.true_residual(U, s, x, dims, 0.14) <= 1e-10
