@@ -14,7 +14,12 @@ divided by the step's wall time. ``roofline`` describes the dominant kernel
 (the FP32 even-odd hopping term) timed with HIP events on the stream it runs
 on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice.
 Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
-and every Dslash variant's GB/s and GFLOP/s.
+the same solve with FP16-storage inner iterations, every Dslash variant's GB/s
+and GFLOP/s, the 12 point sources of a 24^3 x 48 propagator (batched operator
+and batched solve against single ones), an uneven batch of 64 small lattices
+(one call against 64 solves), and a served Poisson stream of mixed-size
+requests (saturation rate, p50/p99 latency at 0.5 and 0.8 of it, and the
+plain FP64 solver one request at a time on the same stream).
 """
 import argparse
 import json
@@ -53,6 +58,10 @@ def parse():
     ap.add_argument("--kernel-launches", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 12-point-source and 64-lattice batch measurements")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
@@ -229,6 +238,145 @@ def uneven64(w, torch, synth, np):
     return out
 
 
+SERVE_SIZES = (((8, 8, 8, 8), 0.40), ((16, 16, 16, 32), 0.35), ((24, 24, 24, 48), 0.20),
+               ((32, 32, 32, 64), 0.05))
+
+
+def serving(w, torch, synth, np, n_req, budget_gb, slots):
+    """Poisson stream of solve requests against 8 resident gauge fields (two
+    exp(i 0.3 H) fields per lattice size, seeds 0..7): sizes 8^4 40 %, 16^3x32
+    35 %, 24^3x48 20 %, 32^3x64 5 %; kappa uniform in [0.12, 0.155]; Gaussian
+    sources (two per size, drawn once); arrivals, sizes, kappas and choices
+    from seed 4. First the closed-loop saturation rate S (every request queued
+    at once), then open-loop streams at 0.5 S and 0.8 S through the server
+    (mixed precision, FP16-storage inner solve, `slots` concurrent solves,
+    HBM budget for workspaces), then the 0.5 S stream through a one-slot
+    plain-FP64 server. Latency = arrival to solution ready."""
+    import queue
+    import threading
+    t = time.time()
+    fields, sources, xpool = {}, {}, {}
+    npool = {0: 128, 1: 64, 2: 24, 3: 12}
+    for k, (dims, _) in enumerate(SERVE_SIZES):
+        fields[k] = [w.pack_gauge(synth.gauge_smooth(dims, 0.30, 2 * k + j), dims)
+                     for j in range(2)]
+        sources[k] = [w.pack_spinor(synth.gaussian_spinor(dims, 100 + 2 * k + j), dims)
+                      for j in range(2)]
+        xpool[k] = queue.Queue()
+        for _ in range(npool[k]):
+            xpool[k].put(w.zeros_spinor(dims))
+    log("serving inputs generated in %.1f s" % (time.time() - t))
+    probs = np.array([p for _, p in SERVE_SIZES])
+
+    def draw(n, seed):
+        rng = np.random.default_rng(seed)
+        size = rng.choice(len(SERVE_SIZES), size=n, p=probs)
+        kappa = rng.uniform(0.12, 0.155, size=n)
+        fld = rng.integers(0, 2, size=n)
+        src = rng.integers(0, 2, size=n)
+        gaps = rng.exponential(1.0, size=n)   # unit-rate inter-arrival gaps
+        return size, kappa, fld, src, gaps
+
+    def run(flags, nslots, rate, n, seed, warm):
+        """One stream; rate None = closed loop (all queued at t = 0)."""
+        size, kappa, fld, src, gaps = draw(n + warm, seed)
+        arrive = np.zeros(n + warm) if rate is None else np.cumsum(gaps) / rate
+        lat, lag, status, iters = [], [], [], []
+        done_t = []
+        srv = w.Server(hbm_budget=int(budget_gb * (1 << 30)), slots=nslots, flags=flags)
+        held = {}
+        stalls = [0]
+
+        submitted = threading.Semaphore(0)
+        errors = []
+
+        def collector():
+            try:
+                for j in range(n + warm):
+                    submitted.acquire()          # next() needs an uncollected request
+                    ticket, code, st, tm = srv.next()
+                    i, k, x, late = held.pop(ticket)
+                    xpool[k].put(x)
+                    if i >= warm:
+                        lat.append(tm["finished"] - tm["submitted"] + late)
+                        status.append(st["status"])
+                        iters.append(st["iterations"])
+                        done_t.append(tm["finished"])
+                    if (j + 1) % 250 == 0:
+                        log("  %d of %d requests done" % (j + 1, n + warm))
+            except Exception as e:               # surfaced by the submitting thread
+                errors.append(e)
+
+        th = threading.Thread(target=collector, daemon=True)
+        th.start()
+        t0 = time.perf_counter()
+        first = None
+        for i in range(n + warm):
+            dt = arrive[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            k = int(size[i])
+            try:
+                x = xpool[k].get_nowait()
+            except queue.Empty:
+                stalls[0] += 1
+                while True:
+                    if errors:
+                        raise errors[0]
+                    try:
+                        x = xpool[k].get(timeout=1.0)
+                        break
+                    except queue.Empty:
+                        pass
+            dims = SERVE_SIZES[k][0]
+            late = max(0.0, (time.perf_counter() - t0) - arrive[i])
+            p = w.Problem(dims, float(kappa[i]), fields[k][int(fld[i])], sources[k][int(src[i])], x)
+            held[i + 1] = (i, k, x, late)        # a new server numbers its tickets 1, 2, ...
+            tk = srv.submit(p)
+            assert tk == i + 1
+            submitted.release()
+            if i == warm:
+                first = time.perf_counter()
+        while th.is_alive():
+            th.join(timeout=1.0)
+            if errors:
+                raise errors[0]
+        if errors:
+            raise errors[0]
+        span = time.perf_counter() - first
+        srv.close()
+        lat = np.array(lat) * 1e3
+        ok = int(sum(1 for s in status if s == 0))
+        return {"requests": n, "warmup_requests": warm, "slots": nslots,
+                "offered_rate": rate, "solves_per_s": n / span,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                "converged": ok, "mean_iterations": float(np.mean(iters)),
+                "buffer_stalls": stalls[0]}
+
+    mixed = w.EO | w.MIXED | w.F16S
+    out = {"hbm_budget_gb": budget_gb, "sizes": [[list(d), p] for d, p in SERVE_SIZES],
+           "kappa": [0.12, 0.155], "resident_fields": 8, "solver": "eo CG, FP16-storage inner, "
+           "FP64 reliable updates, tol 1e-10"}
+    sat = run(mixed, slots, None, max(100, n_req // 4), 40, 10)
+    S = sat["solves_per_s"]
+    log("serving: closed-loop saturation %.1f solves/s" % S)
+    out["closed_loop"] = sat
+    out["saturation_solves_per_s"] = S
+    for frac, seed in ((0.5, 4), (0.8, 41)):
+        r = run(mixed, slots, frac * S, n_req, seed, 20)
+        out["open_loop_%.1fS" % frac] = r
+        log("serving: %.1f S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
+            % (frac, r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
+    r = run(w.EO, 1, 0.5 * S, n_req, 4, 20)
+    out["fp64_one_at_a_time_0.5S"] = r
+    log("serving: FP64 one at a time at 0.5 S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
+        % (r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
+    del fields, sources, xpool
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +528,14 @@ def main():
         uneven = uneven64(w, torch, synth, np)
         log("batch measurements in %.1f s" % (time.time() - t))
 
+    serve = None
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        t = time.time()
+        serve = serving(w, torch, synth, np, args.serving_requests, args.serving_budget_gb,
+                        args.serving_slots)
+        log("serving measurements in %.1f s" % (time.time() - t))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -429,6 +585,7 @@ def main():
         "cpu_baseline": cpu,
         "batch12_point_sources": batch,
         "uneven64_lattices": uneven,
+        "serving": serve,
     }
     print(json.dumps(out))
     return 0

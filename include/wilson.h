@@ -275,7 +275,8 @@ typedef struct {
 int wl_server_create(const wl_server_config *cfg, wl_server **out);
 
 /* Queue a solve of M x = b for one problem (dims, kappa, packed FP64 gauge,
- * b and x as in wl_problem). Non-blocking; *ticket identifies the request.
+ * b and x as in wl_problem). Non-blocking; *ticket identifies the request
+ * (a server numbers its tickets 1, 2, 3, ... in submission order).
  * WL_EINVAL for a bad problem, WL_EWORKSPACE when its workspace exceeds the
  * whole arena (it could never be admitted). */
 int wl_server_submit(wl_server *srv, const wl_problem *p, uint64_t *ticket);
