@@ -6,7 +6,7 @@
 #include <cstring>
 #include <string>
 
-#include "wl_internal.h"
+#include "wl_host.h"
 
 namespace wl {
 

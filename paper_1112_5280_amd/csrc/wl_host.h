@@ -1,0 +1,54 @@
+// wl_host.h -- host-side drivers of libwilson.so (not installed): the Krylov
+// solvers, batched and multi-problem solves, and the solve server. Kernels do
+// not include this header.
+#pragma once
+
+#include "wl_internal.h"
+
+namespace wl {
+
+// ---- solvers ---------------------------------------------------------------
+size_t workspace_bytes(const Geom &g, uint32_t flags);
+
+struct SolveIn {
+    const void *gauge, *b;
+    void *x;
+    Geom g;
+    double kappa;
+    Phases ph;
+    double tol;
+    int maxiter;
+    uint32_t flags;
+    void *work;
+    hipStream_t s;
+    // batches of independent problems (one lattice size): per-RHS gauge
+    // fields (device table) and hopping parameters (host array)
+    const void *const *gtab = nullptr;
+    const double *kappas = nullptr;
+    bool own_stream = false;   // `s` belongs to the library: capture on it directly
+};
+
+int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why);
+
+// batched CG (FP64, full or even-odd): nrhs fields of b and x, st[nrhs]
+size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs);
+int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why);
+
+// independent problems of several lattice sizes, solved concurrently
+size_t problems_workspace_bytes(const wl_problem *p, int n, uint32_t flags);
+int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int maxiter,
+                 uint32_t flags, void *work, hipStream_t caller, wl_solve_stats *st,
+                 std::string *why);
+
+// the solve server (wl_server.hip); wl_server itself is the opaque C type
+int server_create(const wl_server_config &cfg, const Phases &ph, wl_server **out, std::string *why);
+int server_submit(wl_server *s, const wl_problem &p, const Geom &g, uint64_t *ticket,
+                  std::string *why);
+int server_wait(wl_server *s, uint64_t ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why);
+int server_next(wl_server *s, uint64_t *ticket, wl_solve_stats *st, wl_request_times *t,
+                std::string *why);
+int server_pending(wl_server *s);
+int server_destroy(wl_server *s);
+
+}  // namespace wl

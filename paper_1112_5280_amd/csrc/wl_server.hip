@@ -18,7 +18,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "wl_internal.h"
+#include "wl_host.h"
 
 namespace wl {
 namespace {

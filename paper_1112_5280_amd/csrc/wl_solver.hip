@@ -24,7 +24,7 @@
 #include <thread>
 #include <vector>
 
-#include "wl_internal.h"
+#include "wl_host.h"
 
 namespace wl {
 
