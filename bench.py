@@ -189,6 +189,7 @@ def batch12(w, torch, synth, n_launch):
     out["solves"] = solves
     out["batched_vs_sequential_f64"] = (solves["sequential_f64_eo"]["seconds"] /
                                         solves["batched_f64_eo"]["seconds"])
+    out["autotuned_rhs_per_thread"] = w.tuning_report().strip().splitlines()
     del G, B, X, X1
     torch.cuda.empty_cache()
     return out

@@ -235,6 +235,17 @@ int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], do
                       int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream);
 
+/* Autotuning record. Batched operator launches (wilson_dslash_batch and the
+ * batched solves) give each thread several right-hand sides at once, so one
+ * link load serves all of them; the first launch of each shape (precision,
+ * link format, operator, batch size, lattice) times every candidate count on
+ * its own buffers and keeps the fastest (environment: WL_TUNE=0 disables
+ * tuning, WL_TUNE_FILE=path keeps the choices in that file across processes).
+ * Copies the record, one line per shape with the chosen count and the time of
+ * each candidate, into buf (at most len - 1 bytes and a NUL; buf may be NULL)
+ * and returns its full length. */
+size_t wl_tuning_report(char *buf, size_t len);
+
 /* ---------------------------------------------------------------------------
  * Serving: a solve server that admits requests as device memory and solve
  * slots free up, and runs the admitted solves concurrently (paper Sec. 4: many

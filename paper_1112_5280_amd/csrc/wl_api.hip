@@ -1,6 +1,7 @@
 // wl_api.hip -- the extern "C" boundary of libwilson.so (declared in
 // include/wilson.h): argument validation, error reporting and dispatch to the
 // launchers and solver drivers. No exception crosses this boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -439,6 +440,16 @@ int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims
                    void *stream) {
     return solve_common(true, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
                         work_bytes, stats, stream);
+}
+
+size_t wl_tuning_report(char *buf, size_t len) {
+    const std::string r = tuning_report();
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, r.size());
+        std::memcpy(buf, r.data(), n);
+        buf[n] = '\0';
+    }
+    return r.size();
 }
 
 int wl_server_create(const wl_server_config *cfg, wl_server **out) {

@@ -25,6 +25,13 @@
 // Model cost: 1320 flop per output site for the hopping term, +48 for the
 // xpay; compulsory bytes: 8 links and 8 neighbour spinors amortised over the
 // lattice (see the layout notes in wilson.h).
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
 #include "wl_internal.h"
 #include "wl_reduce.h"
 
@@ -50,6 +57,8 @@
 
 namespace wl {
 
+constexpr int kMaxNr = 4;   // right-hand sides per thread in batched launches
+
 template <typename ST>
 struct MinWaves {
     static constexpr int value = std::is_same<ST, double>::value ? WL_F64_WAVES : WL_F32_WAVES;
@@ -67,8 +76,9 @@ struct HopArgs {
     Geom g;
     int first_par;         // parity of the first output block
     int npar;              // output parities in this launch (1 or 2)
-    int nblocks;           // nb_rhs * nrhs
+    int nblocks;           // nb_rhs * ngroups
     int nb_rhs;            // blocks per right-hand side
+    int ngroups;           // RHS groups (NR right-hand sides per thread)
     int nrhs;              // right-hand sides (fields fstride bytes apart)
     size_t fstride;
     R c;
@@ -166,47 +176,121 @@ __device__ __forceinline__ void times_phase(cpx<R> o[6], R pr, R pi) {
     for (int k = 0; k < 6; ++k) o[k] = ph * o[k];
 }
 
-// One hop direction: forward (FWD) or backward, projector sign S.
-template <typename ST, int NCL, int MU, int S, bool FWD>
+// One hop direction, forward (FWD) or backward, projector sign S, applied to
+// the NR right-hand sides a thread owns: the link is loaded (and for 12-real
+// storage rebuilt) once and multiplies the projected neighbour of every RHS.
+template <typename ST, int NCL, int MU, int S, bool FWD, int NR>
 __device__ __forceinline__ void hop_dir(const HopArgs<Real<ST>> &a, const void *gauge,
-                                        const void *in_blk, int p, int i, int nb, bool wrap,
-                                        cpx<Real<ST>> acc[12]) {
+                                        const char *const (&in_blk)[NR], const bool (&on)[NR],
+                                        int p, int i, int nb, bool wrap,
+                                        cpx<Real<ST>> (&acc)[NR][12]) {
     using R = Real<ST>;
-    cpx<R> psi[12];
-    load_spinor<ST>(in_blk, a.g.S, nb, psi);
-    cpx<R> h[6];
-    project<MU, S>(psi, h);
     cpx<R> u[9];
-    cpx<R> o[6];
-    if constexpr (FWD) {
-        load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
-        su3_mul(u, h, o);
-        if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
-    } else {
-        load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
-        su3_dag_mul(u, h, o);
-        if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
+    if constexpr (NR == 1) {
+        // one RHS: neighbour spinor first, then the link (the order the
+        // register allocation of the single-field kernels is best with)
+        cpx<R> psi[12];
+        load_spinor<ST>(in_blk[0], a.g.S, nb, psi);
+        cpx<R> h[6];
+        project<MU, S>(psi, h);
+        cpx<R> o[6];
+        if constexpr (FWD) {
+            load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
+            su3_mul(u, h, o);
+            if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
+        } else {
+            load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
+            su3_dag_mul(u, h, o);
+            if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
+        }
+        accumulate<MU, S>(acc[0], o);
+        return;
     }
-    accumulate<MU, S>(acc, o);
+    if constexpr (FWD)
+        load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
+    else
+        load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (NR > 1 && !on[r]) continue;
+        cpx<R> psi[12];
+        load_spinor<ST>(in_blk[r], a.g.S, nb, psi);
+        cpx<R> h[6];
+        project<MU, S>(psi, h);
+        cpx<R> o[6];
+        if constexpr (FWD) {
+            su3_mul(u, h, o);
+            if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
+        } else {
+            su3_dag_mul(u, h, o);
+            if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
+        }
+        accumulate<MU, S>(acc[r], o);
+    }
 }
 
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
+// Block partials of NR right-hand sides at once: the same shuffle tree and
+// wave order as block_partial, so every RHS's partial is bitwise the one a
+// single-RHS launch would store.
+template <int NS, int NR>
+__device__ __forceinline__ void block_partial_rhs(double (&v)[NR][NS], const bool (&on)[NR],
+                                                  const Reduce &red, int rhs0, int slot, int nb) {
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh[kWaves][NR][NS];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[r][s] += __shfl_xor(v[r][s], off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) sh[wave][r][s] = v[r][s];
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r < NR && on[r]) {
+        double *partials = rhs_reduce(red, rhs0 + r, nb).partials;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) t += sh[w][r][s];
+            partials[s * nb + slot] = t;
+        }
+    }
+}
+
+// NR right-hand sides per thread (register blocking over the batch): the
+// logical block index runs over (site block, RHS group) with the group
+// fastest, so the groups sharing a site range run back to back on one XCD.
+template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
 __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArgs<Real<ST>> a) {
     using R = Real<ST>;
     const Geom &g = a.g;
-    // logical block -> (right-hand side, block of that field); the RHS index
-    // runs fastest so the blocks sharing a site range (and its links) are
-    // consecutive and land on one XCD
     const int bl = WL_XCD_REMAP ? xcd_block(blockIdx.x, a.nblocks) : int(blockIdx.x);
-    const int rhs = bl % a.nrhs;
-    const int b = bl / a.nrhs;
-    if (rhs_skip(a.skip, rhs)) return;
-    const size_t fo = size_t(rhs) * a.fstride;
-    const void *gauge = a.gtab ? a.gtab[rhs] : a.gauge;
-    R c = a.c;
-    if (a.ksc) {
-        const R k = R(a.ksc[rhs].kappa);
-        c = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
+    const int q = bl % a.ngroups;
+    const int b = bl / a.ngroups;
+    const int rhs0 = q * NR;
+    bool on[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        on[r] = rhs0 + r < a.nrhs && !rhs_skip(a.skip, rhs0 + r);
+        any = any || on[r];
+    }
+    if (!any) return;
+    const void *gauge = a.gtab ? a.gtab[rhs0] : a.gauge;   // gtab only with NR = 1
+    R c[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        c[r] = a.c;
+        if (a.ksc) {
+            const R k = R(a.ksc[rhs0 + r].kappa);
+            c[r] = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
+        }
     }
     int pidx, bi;
     if (WL_PAR_INTERLEAVE && a.npar == 2) {
@@ -220,129 +304,335 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
     const int i = bi * kBlock + threadIdx.x;
 
     constexpr int NS = RED == kRedNone ? 1 : (RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3));
-    double sums[NS];
+    double sums[NR][NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sums[s] = 0.0;
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) sums[r][s] = 0.0;
 
     if (i < g.Vh) {
         // coordinates of the output site
         const int xh = i % g.Lxh;
-        int r = i / g.Lxh;
-        const int y = r % g.L[1];
-        r /= g.L[1];
-        const int z = r % g.L[2];
-        const int t = r / g.L[2];
+        int rr = i / g.Lxh;
+        const int y = rr % g.L[1];
+        rr /= g.L[1];
+        const int z = rr % g.L[2];
+        const int t = rr / g.L[2];
         const int x = 2 * xh + ((y + z + t + p) & 1);
 
-        const void *in_blk = static_cast<const char *>(a.in[1 - p]) + fo;
+        size_t fo[NR];
+        const char *in_blk[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            fo[r] = size_t(rhs0 + r) * a.fstride;
+            in_blk[r] = static_cast<const char *>(a.in[1 - p]) + fo[r];
+        }
         constexpr int SF = DAG ? 1 : -1;   // forward projector 1 + SF gamma
         constexpr int SB = -SF;            // backward projector 1 + SB gamma
 
-        cpx<R> acc[12];
+        cpx<R> acc[NR][12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[k] = {R(0), R(0)};
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[r][k] = {R(0), R(0)};
 
         {   // x direction: neighbour checkerboard index changes through x/2
             const int xp = (x + 1 == g.L[0]) ? 0 : x + 1;
             const int xm = (x == 0) ? g.L[0] - 1 : x - 1;
-            hop_dir<ST, NCL, 0, SF, true>(a, gauge, in_blk, p, i,i - xh + (xp >> 1), x == g.L[0] - 1, acc);
-            hop_dir<ST, NCL, 0, SB, false>(a, gauge, in_blk, p, i,i - xh + (xm >> 1), x == 0, acc);
+            hop_dir<ST, NCL, 0, SF, true, NR>(a, gauge, in_blk, on, p, i, i - xh + (xp >> 1),
+                                              x == g.L[0] - 1, acc);
+            hop_dir<ST, NCL, 0, SB, false, NR>(a, gauge, in_blk, on, p, i, i - xh + (xm >> 1),
+                                               x == 0, acc);
         }
         {
             const int st = g.Lxh;
             const int span = (g.L[1] - 1) * st;
-            hop_dir<ST, NCL, 1, SF, true>(a, gauge, in_blk, p, i,y == g.L[1] - 1 ? i - span : i + st,
-                                          y == g.L[1] - 1, acc);
-            hop_dir<ST, NCL, 1, SB, false>(a, gauge, in_blk, p, i,y == 0 ? i + span : i - st, y == 0, acc);
+            hop_dir<ST, NCL, 1, SF, true, NR>(a, gauge, in_blk, on, p, i,
+                                              y == g.L[1] - 1 ? i - span : i + st,
+                                              y == g.L[1] - 1, acc);
+            hop_dir<ST, NCL, 1, SB, false, NR>(a, gauge, in_blk, on, p, i,
+                                               y == 0 ? i + span : i - st, y == 0, acc);
         }
         {
             const int st = g.Lxh * g.L[1];
             const int span = (g.L[2] - 1) * st;
-            hop_dir<ST, NCL, 2, SF, true>(a, gauge, in_blk, p, i,z == g.L[2] - 1 ? i - span : i + st,
-                                          z == g.L[2] - 1, acc);
-            hop_dir<ST, NCL, 2, SB, false>(a, gauge, in_blk, p, i,z == 0 ? i + span : i - st, z == 0, acc);
+            hop_dir<ST, NCL, 2, SF, true, NR>(a, gauge, in_blk, on, p, i,
+                                              z == g.L[2] - 1 ? i - span : i + st,
+                                              z == g.L[2] - 1, acc);
+            hop_dir<ST, NCL, 2, SB, false, NR>(a, gauge, in_blk, on, p, i,
+                                               z == 0 ? i + span : i - st, z == 0, acc);
         }
         {
             const int st = g.Lxh * g.L[1] * g.L[2];
             const int span = (g.L[3] - 1) * st;
-            hop_dir<ST, NCL, 3, SF, true>(a, gauge, in_blk, p, i,t == g.L[3] - 1 ? i - span : i + st,
-                                          t == g.L[3] - 1, acc);
-            hop_dir<ST, NCL, 3, SB, false>(a, gauge, in_blk, p, i,t == 0 ? i + span : i - st, t == 0, acc);
+            hop_dir<ST, NCL, 3, SF, true, NR>(a, gauge, in_blk, on, p, i,
+                                              t == g.L[3] - 1 ? i - span : i + st,
+                                              t == g.L[3] - 1, acc);
+            hop_dir<ST, NCL, 3, SB, false, NR>(a, gauge, in_blk, on, p, i,
+                                               t == 0 ? i + span : i - st, t == 0, acc);
         }
 
-        cpx<R> o[12];
-        cpx<R> xv[12];
-        if constexpr (XPAY) {
-            load_spinor<ST>(static_cast<const char *>(a.xs[p]) + fo, g.S, i, xv);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) o[k] = xv[k] + c * acc[k];
-        } else {
+        for (int r = 0; r < NR; ++r) {
+            if (NR > 1 && !on[r]) continue;
+            cpx<R> o[12];
+            cpx<R> xv[12];
+            if constexpr (XPAY) {
+                load_spinor<ST>(static_cast<const char *>(a.xs[p]) + fo[r], g.S, i, xv);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) o[k] = c * acc[k];
-        }
-        store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo, g.S, i, o);
-
-        if constexpr (RED == kRedNorm) {
+                for (int k = 0; k < 12; ++k) o[k] = xv[k] + c[r] * acc[r][k];
+            } else {
 #pragma unroll
-            for (int k = 0; k < 12; ++k)
-                sums[0] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
-        } else if constexpr (RED == kRedDotAux) {   // <aux, out>
-            cpx<R> w[12];
-            load_spinor<ST>(static_cast<const char *>(a.aux[p]) + fo, g.S, i, w);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                sums[0] += double(w[k].re) * double(o[k].re) + double(w[k].im) * double(o[k].im);
-                sums[1] += double(w[k].re) * double(o[k].im) - double(w[k].im) * double(o[k].re);
+                for (int k = 0; k < 12; ++k) o[k] = c[r] * acc[r][k];
             }
-        } else if constexpr (RED == kRedTS) {       // <out, xs>, ||out||^2
-            static_assert(XPAY, "kRedTS needs the xpay source");
+            store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo[r], g.S, i, o);
+
+            double *sm = sums[r];
+            if constexpr (RED == kRedNorm) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                sums[0] += double(o[k].re) * double(xv[k].re) + double(o[k].im) * double(xv[k].im);
-                sums[1] += double(o[k].re) * double(xv[k].im) - double(o[k].im) * double(xv[k].re);
-                sums[2] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
+                for (int k = 0; k < 12; ++k)
+                    sm[0] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
+            } else if constexpr (RED == kRedDotAux) {   // <aux, out>
+                cpx<R> w[12];
+                load_spinor<ST>(static_cast<const char *>(a.aux[p]) + fo[r], g.S, i, w);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    sm[0] += double(w[k].re) * double(o[k].re) + double(w[k].im) * double(o[k].im);
+                    sm[1] += double(w[k].re) * double(o[k].im) - double(w[k].im) * double(o[k].re);
+                }
+            } else if constexpr (RED == kRedTS) {       // <out, xs>, ||out||^2
+                static_assert(XPAY, "kRedTS needs the xpay source");
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    sm[0] += double(o[k].re) * double(xv[k].re) + double(o[k].im) * double(xv[k].im);
+                    sm[1] += double(o[k].re) * double(xv[k].im) - double(o[k].im) * double(xv[k].re);
+                    sm[2] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
+                }
             }
         }
     }
-    if constexpr (RED != kRedNone)
-        block_partial<NS>(sums, rhs_reduce(a.red, rhs, a.nb_rhs).partials, b, a.nb_rhs);
+    if constexpr (RED != kRedNone) {
+        if constexpr (NR == 1)
+            block_partial<NS>(sums[0], rhs_reduce(a.red, rhs0, a.nb_rhs).partials, b, a.nb_rhs);
+        else
+            block_partial_rhs<NS, NR>(sums, on, a.red, rhs0, b, a.nb_rhs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
+static hipError_t launch_kernel(HopArgs<Real<ST>> a, hipStream_t s) {
+    a.ngroups = (a.nrhs + NR - 1) / NR;
+    a.nblocks = a.nb_rhs * a.ngroups;
+    hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED, NR>), dim3(a.nblocks), dim3(kBlock),
+                       0, s, a);
+    return hipGetLastError();
+}
+
+// RHS per thread the kernels are built for (register blocking of batches):
+// FP64 and FP32 storage, no reduction or a norm; FP16 storage and the
+// BiCGStab reductions use one.
+template <typename ST, int RED>
+constexpr bool blocked_ok() {
+    return !std::is_same<ST, Half>::value && (RED == kRedNone || RED == kRedNorm);
 }
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_t(const HopArgs<Real<ST>> &a, hipStream_t s) {
-    hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED>), dim3(a.nblocks), dim3(kBlock), 0, s,
-                       a);
-    const hipError_t e = hipGetLastError();
+static hipError_t launch_nr(const HopArgs<Real<ST>> &a, int nr, hipStream_t s) {
+    if constexpr (blocked_ok<ST, RED>()) {
+        switch (nr) {
+        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, s);
+        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, s);
+        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, s);
+        default: break;
+        }
+    }
+    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, s);
+}
+
+// ---- autotuning of the RHS blocking ----------------------------------------
+// The first batched launch of each shape (precision, links, operator,
+// reduction, batch size, lattice) times every candidate RHS-per-thread count
+// on the call's own buffers, when that is safe (no graph capture under way,
+// the output aliases no input: the kernel is then idempotent and every
+// candidate writes the same bits), and keeps the fastest. Choices are cached
+// per process and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables
+// tuning (fixed default).
+namespace {
+
+struct TuneEntry {
+    int nr;
+    float us[kMaxNr + 1];   // average launch time per candidate (0: not timed)
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, int red,
+                     int nrhs, int npar) {
+    char k[160];
+    std::snprintf(k, sizeof k, "hop prec=%d link=%d dag=%d xpay=%d red=%d nrhs=%d npar=%d "
+                               "L=%dx%dx%dx%d",
+                  prec, link12 ? 12 : 18, int(dag), int(xpay), red, nrhs, npar, g.L[0], g.L[1],
+                  g.L[2], g.L[3]);
+    return k;
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("WL_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char *bar = std::strrchr(line, '|');
+        if (!bar) continue;
+        int nr = 0;
+        if (std::sscanf(bar + 1, " nr=%d", &nr) != 1 || nr < 1 || nr > kMaxNr) continue;
+        std::string key(line, bar - line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        TuneEntry e{};
+        e.nr = nr;
+        g_tune[key] = e;
+    }
+    std::fclose(f);
+}
+
+void tune_store_locked(const std::string &key, const TuneEntry &e) {
+    g_tune[key] = e;
+    const char *path = std::getenv("WL_TUNE_FILE");
+    if (!path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s | nr=%d\n", key.c_str(), e.nr);
+        std::fclose(f);
+    }
+}
+
+bool tuning_enabled() {
+    const char *v = std::getenv("WL_TUNE");
+    return !(v && v[0] == '0');
+}
+
+}  // namespace
+
+std::string tuning_report() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string out;
+    for (const auto &kv : g_tune) {
+        char buf[64];
+        out += kv.first;
+        std::snprintf(buf, sizeof buf, " | nr=%d", kv.second.nr);
+        out += buf;
+        for (int n = 1; n <= kMaxNr; ++n)
+            if (kv.second.us[n] > 0) {
+                std::snprintf(buf, sizeof buf, " t%d=%.1fus", n, kv.second.us[n]);
+                out += buf;
+            }
+        out += "\n";
+    }
+    return out;
+}
+
+template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
+static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
+                               bool link12, hipStream_t s) {
+    constexpr int kDefaultNr = std::is_same<ST, double>::value ? 2 : 4;
+    if (!blocked_ok<ST, RED>() || a.nrhs < 2 || a.gtab) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, 1, s);
+    const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, it->second.nr, s);
+    }
+    // is it safe to time the candidates on this call?
+    bool safe = tuning_enabled();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (safe && (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone))
+        safe = false;
+    for (int q = 0; q < 2 && safe; ++q) {
+        const int po = a.first_par ^ q;
+        if (q >= a.npar) break;
+        const void *o = a.out[po];
+        if (o == a.in[1 - po] || o == a.xs[po] || o == a.aux[po] || o == a.in[po]) safe = false;
+    }
+    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, kDefaultNr, s);
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    TuneEntry best{};
+    best.nr = kDefaultNr;
+    float best_t = 1e30f;
+    constexpr int kReps = 3;
+    for (int nr = 1; nr <= kMaxNr && err == hipSuccess; ++nr) {
+        if (nr > a.nrhs) break;
+        err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, nr, s);   // warm-up
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int k = 0; k < kReps && err == hipSuccess; ++k)
+            err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, nr, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) break;
+        best.us[nr] = 1e3f * ms / kReps;
+        if (best.us[nr] < best_t) {
+            best_t = best.us[nr];
+            best.nr = nr;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return err;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(key, best);
+    }
+    // leave the chosen variant's result in place
+    return launch_nr<ST, NCL, DAG, XPAY, RED>(a, best.nr, s);
+}
+
+template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
+static hipError_t launch_t(const HopArgs<Real<ST>> &a, const HopCall &call, int prec, bool link12,
+                           hipStream_t s) {
+    const hipError_t e = launch_tuned<ST, NCL, DAG, XPAY, RED>(a, call, prec, link12, s);
     if (e != hipSuccess || RED == kRedNone) return e;
     constexpr int NS = RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3);
     return launch_finish(a.red, NS, a.nb_rhs, a.nrhs, a.skip, s);
 }
 
 template <typename ST, int NCL, bool DAG, bool XPAY>
-static hipError_t launch_red(const HopArgs<Real<ST>> &a, int red, hipStream_t s) {
+static hipError_t launch_red(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
+                             bool link12, int red, hipStream_t s) {
     switch (red) {
-    case kRedNone: return launch_t<ST, NCL, DAG, XPAY, kRedNone>(a, s);
-    case kRedNorm: return launch_t<ST, NCL, DAG, XPAY, kRedNorm>(a, s);
-    case kRedDotAux: return launch_t<ST, NCL, DAG, XPAY, kRedDotAux>(a, s);
+    case kRedNone: return launch_t<ST, NCL, DAG, XPAY, kRedNone>(a, call, prec, link12, s);
+    case kRedNorm: return launch_t<ST, NCL, DAG, XPAY, kRedNorm>(a, call, prec, link12, s);
+    case kRedDotAux: return launch_t<ST, NCL, DAG, XPAY, kRedDotAux>(a, call, prec, link12, s);
     default:
-        if constexpr (XPAY) return launch_t<ST, NCL, DAG, XPAY, kRedTS>(a, s);
+        if constexpr (XPAY) return launch_t<ST, NCL, DAG, XPAY, kRedTS>(a, call, prec, link12, s);
         return hipErrorInvalidValue;
     }
 }
 
 template <typename ST, int NCL>
-static hipError_t launch_ncl(const HopArgs<Real<ST>> &a, bool dag, bool xpay, int red,
-                             hipStream_t s) {
+static hipError_t launch_ncl(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
+                             bool link12, bool dag, bool xpay, int red, hipStream_t s) {
     if (dag) {
-        return xpay ? launch_red<ST, NCL, true, true>(a, red, s)
-                    : launch_red<ST, NCL, true, false>(a, red, s);
+        return xpay ? launch_red<ST, NCL, true, true>(a, call, prec, link12, red, s)
+                    : launch_red<ST, NCL, true, false>(a, call, prec, link12, red, s);
     }
-    return xpay ? launch_red<ST, NCL, false, true>(a, red, s)
-                : launch_red<ST, NCL, false, false>(a, red, s);
+    return xpay ? launch_red<ST, NCL, false, true>(a, call, prec, link12, red, s)
+                : launch_red<ST, NCL, false, false>(a, call, prec, link12, red, s);
 }
 
 template <typename ST>
-static hipError_t launch_storage(const Geom &g, bool link12, const Phases &ph,
+static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Phases &ph,
                                  const HopCall &call, int red, hipStream_t s) {
     using R = Real<ST>;
     HopArgs<R> a;
@@ -358,6 +648,7 @@ static hipError_t launch_storage(const Geom &g, bool link12, const Phases &ph,
     a.npar = call.npar;
     a.nrhs = call.nrhs < 1 ? 1 : call.nrhs;
     a.nb_rhs = g.bpp * call.npar;
+    a.ngroups = a.nrhs;
     a.nblocks = a.nb_rhs * a.nrhs;
     a.fstride = call.fstride;
     a.c = R(call.c);
@@ -373,8 +664,8 @@ static hipError_t launch_storage(const Geom &g, bool link12, const Phases &ph,
     a.cmul = R(call.cmul);
     a.cpow = call.cpow;
     const bool xpay = call.xs[call.first_par] != nullptr;
-    return link12 ? launch_ncl<ST, 6>(a, call.dag, xpay, red, s)
-                  : launch_ncl<ST, 9>(a, call.dag, xpay, red, s);
+    return link12 ? launch_ncl<ST, 6>(a, call, prec, link12, call.dag, xpay, red, s)
+                  : launch_ncl<ST, 9>(a, call, prec, link12, call.dag, xpay, red, s);
 }
 
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
@@ -392,7 +683,7 @@ hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
         !call.in[1 - call.first_par])
         return hipErrorInvalidValue;
     return with_storage(prec, [&](auto tag) {
-        return launch_storage<decltype(tag)>(g, link12, ph, call, red, s);
+        return launch_storage<decltype(tag)>(g, prec, link12, ph, call, red, s);
     });
 }
 

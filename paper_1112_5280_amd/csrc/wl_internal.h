@@ -287,6 +287,8 @@ struct HopCall {
 };
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s);
+// The autotuner's choices so far, one line per tuned batched-operator shape.
+std::string tuning_report();
 
 // Canonical complex128 <-> packed
 hipError_t launch_pack_gauge(const Geom &g, int prec, bool link12, const void *canon,

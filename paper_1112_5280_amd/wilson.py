@@ -47,7 +47,7 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch",
            "wl_problems_workspace_bytes", "solve_cg_problems",
            "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
-           "wl_server_pending", "wl_server_destroy")
+           "wl_server_pending", "wl_server_destroy", "wl_tuning_report")
 
 
 class WilsonError(RuntimeError):
@@ -132,6 +132,8 @@ def _load():
     lib.wl_server_pending.restype = I32
     lib.wl_server_destroy.argtypes = [P]
     lib.wl_server_destroy.restype = ctypes.c_int
+    lib.wl_tuning_report.argtypes = [ctypes.c_char_p, SZ]
+    lib.wl_tuning_report.restype = SZ
     return lib
 
 
@@ -387,6 +389,14 @@ def solve_cg_problems(problems, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000
         d["status_name"] = STATUS_NAMES.get(d["status"], "?")
         out.append(d)
     return code, out
+
+
+def tuning_report():
+    """The autotuner's record: one line per tuned batched-operator shape."""
+    n = lib.wl_tuning_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.wl_tuning_report(buf, n + 1)
+    return buf.value.decode()
 
 
 class Server:

@@ -115,3 +115,29 @@ def test_batch_argument_errors(w):
         w.solve_cg_batch(G, B, w.empty_batch(dims, 3), 3, dims, 0.1, flags=w.MIXED)
     with pytest.raises(w.WilsonError):
         w.wilson_dslash_batch(G, B, B, 3, dims, 0.1)
+
+
+@pytest.mark.parametrize("nrhs", [2, 3, 7, 12])
+@pytest.mark.parametrize("flags", [0x0, 0x1 | 0x8, 0x4], ids=["f64", "f32-dag", "f64-link12"])
+def test_register_blocked_batches_equal_single(w, nrhs, flags):
+    """Every RHS-per-thread count the autotuner tries writes the single-field
+    bits, also for batch sizes that leave the last group partly empty."""
+    dims = (4, 6, 4, 8)
+    kappa = 0.12
+    U = synth.gauge_haar(dims, 4)
+    prec = flags & 0x3
+    G = w.pack_gauge(U, dims, flags & 0x7)
+    B = w.empty_batch(dims, nrhs, prec)
+    for r in range(nrhs):
+        w.batch_field(B, dims, prec, r).copy_(
+            w.pack_spinor(synth.gaussian_spinor(dims, 30 + r), dims, prec))
+    O = w.empty_batch(dims, nrhs, prec)
+    w.wilson_dslash_batch(G, B, O, nrhs, dims, kappa, flags=flags)
+    one = w.empty_spinor(dims, prec)
+    for r in range(nrhs):
+        w.wilson_dslash(G, w.batch_field(B, dims, prec, r), one, dims, kappa, flags=flags)
+        gu.sync()
+        assert np.array_equal(gu.to_np(w.unpack_spinor(w.batch_field(O, dims, prec, r), dims, prec)),
+                              gu.to_np(w.unpack_spinor(one, dims, prec))), r
+    rep = w.tuning_report()
+    assert "nrhs=%d " % nrhs in rep and "L=4x6x4x8" in rep, rep
