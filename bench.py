@@ -412,7 +412,7 @@ def main():
 
     def step():
         w._check(w.lib.wl_pack_spinor(w._ptr(b_dev), w._ptr(B), d4, w.F64, sp), "pack")
-        st = w.solve_cg(G64, B, X, dims, kappa, tol=1e-10, maxiter=200000, flags=flags,
+        st = w.solve_cg(G64, B, X, dims, kappa, tol=1e-10, maxiter=20000, flags=flags,
                         work=work, stream=s)
         w._check(w.lib.wl_unpack_spinor(w._ptr(X), w._ptr(x_dev), d4, w.F64, sp), "unpack")
         return st
@@ -442,7 +442,7 @@ def main():
         w64 = torch.empty(w.workspace_bytes(dims, w.EO | link), dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        st64 = w.solve_cg(G64, B, X64, dims, kappa, tol=1e-10, maxiter=200000,
+        st64 = w.solve_cg(G64, B, X64, dims, kappa, tol=1e-10, maxiter=20000,
                           flags=w.EO | link, work=w64, stream=s)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
@@ -459,10 +459,10 @@ def main():
         f16f = w.EO | w.MIXED | w.F16S | link
         wk = torch.empty(w.workspace_bytes(dims, f16f), dtype=torch.uint8, device="cuda")
         X16 = w.empty_spinor(dims)
-        w.solve_cg(G64, B, X16, dims, kappa, tol=1e-10, maxiter=200000, flags=f16f, work=wk,
+        w.solve_cg(G64, B, X16, dims, kappa, tol=1e-10, maxiter=20000, flags=f16f, work=wk,
                    stream=s)
         st16, dt = timed(lambda: w.solve_cg(G64, B, X16, dims, kappa, tol=1e-10,
-                                            maxiter=200000, flags=f16f, work=wk, stream=s),
+                                            maxiter=20000, flags=f16f, work=wk, stream=s),
                          torch)
         x16 = w.unpack_spinor(X16, dims)
         f16 = {"seconds": dt, "iterations": st16["iterations"], "status": st16["status_name"],

@@ -22,15 +22,20 @@
 // Storage is FP64, FP32 or FP16 (spinors with a per-site scale); arithmetic
 // is FP64 for FP64 storage and FP32 otherwise.
 //
+// With batches of fields, a thread may own several right-hand sides (NR),
+// which then share every link load.
+//
 // Model cost: 1320 flop per output site for the hopping term, +48 for the
 // xpay; compulsory bytes: 8 links and 8 neighbour spinors amortised over the
 // lattice (see the layout notes in wilson.h).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "wl_internal.h"
 #include "wl_reduce.h"
@@ -79,6 +84,7 @@ struct HopArgs {
     int nblocks;           // nb_rhs * ngroups
     int nb_rhs;            // blocks per right-hand side
     int ngroups;           // RHS groups (NR right-hand sides per thread)
+    int chunk;             // site blocks per chunk of the block order
     int nrhs;              // right-hand sides (fields fstride bytes apart)
     size_t fstride;
     R c;
@@ -263,16 +269,24 @@ __device__ __forceinline__ void block_partial_rhs(double (&v)[NR][NS], const boo
     }
 }
 
-// NR right-hand sides per thread (register blocking over the batch): the
-// logical block index runs over (site block, RHS group) with the group
-// fastest, so the groups sharing a site range run back to back on one XCD.
+// NR right-hand sides per thread (register blocking over the batch). The
+// logical block index runs over chunks of `chunk` consecutive site blocks;
+// inside a chunk, over the RHS groups, and inside a group over the chunk's
+// site blocks. chunk = 1 puts the groups that share a site range (and its
+// links) back to back; a larger chunk keeps the neighbour spinors of one group
+// (the z and t neighbours lie many blocks away) in cache while the next group
+// still finds the chunk's links there. The order changes no arithmetic.
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
 __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArgs<Real<ST>> a) {
     using R = Real<ST>;
     const Geom &g = a.g;
     const int bl = WL_XCD_REMAP ? xcd_block(blockIdx.x, a.nblocks) : int(blockIdx.x);
-    const int q = bl % a.ngroups;
-    const int b = bl / a.ngroups;
+    const int ch = bl / (a.chunk * a.ngroups);
+    const int base = ch * a.chunk;
+    const int cl = min(a.chunk, a.nb_rhs - base);        // site blocks in this chunk
+    const int rem = bl - base * a.ngroups;
+    const int q = rem / cl;
+    const int b = base + rem % cl;
     const int rhs0 = q * NR;
     bool on[NR];
     bool any = false;
@@ -422,10 +436,12 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
-static hipError_t launch_kernel(HopArgs<Real<ST>> a, hipStream_t s) {
+static hipError_t launch_kernel(HopArgs<Real<ST>> a, int chunk, hipStream_t s) {
     a.ngroups = (a.nrhs + NR - 1) / NR;
     a.nblocks = a.nb_rhs * a.ngroups;
+    a.chunk = std::max(1, std::min(chunk, a.nb_rhs));
     hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED, NR>), dim3(a.nblocks), dim3(kBlock),
                        0, s, a);
     return hipGetLastError();
@@ -439,32 +455,40 @@ constexpr bool blocked_ok() {
     return !std::is_same<ST, Half>::value && (RED == kRedNone || RED == kRedNorm);
 }
 
+// A launch shape of a batched operator: RHS per thread, site blocks per chunk.
+struct Shape {
+    int nr = 1, chunk = 1;
+};
+
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_nr(const HopArgs<Real<ST>> &a, int nr, hipStream_t s) {
+static hipError_t launch_nr(const HopArgs<Real<ST>> &a, Shape sh, hipStream_t s) {
     if constexpr (blocked_ok<ST, RED>()) {
-        switch (nr) {
-        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, s);
-        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, s);
-        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, s);
+        switch (sh.nr) {
+        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, sh.chunk, s);
+        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, sh.chunk, s);
+        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, sh.chunk, s);
         default: break;
         }
     }
-    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, s);
+    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, sh.chunk, s);
 }
 
-// ---- autotuning of the RHS blocking ----------------------------------------
-// The first batched launch of each shape (precision, links, operator,
-// reduction, batch size, lattice) times every candidate RHS-per-thread count
-// on the call's own buffers, when that is safe (no graph capture under way,
-// the output aliases no input: the kernel is then idempotent and every
-// candidate writes the same bits), and keeps the fastest. Choices are cached
-// per process and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables
-// tuning (fixed default).
+// ---- autotuning of batched launch shapes -----------------------------------
+// The first batched launch of each shape key (precision, links, operator,
+// reduction, batch size, lattice) times candidate launch shapes on the call's
+// own buffers, when that is safe (no graph capture under way, the output
+// aliases no input: the kernel is then idempotent and every candidate writes
+// the same bits), and keeps the fastest: first the RHS-per-thread count with
+// chunk 1, then chunk lengths for that count. Choices are cached per process
+// and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables tuning (fixed
+// default shape).
 namespace {
 
+constexpr int kChunks[] = {1, 4, 16, 64, 1 << 30};
+
 struct TuneEntry {
-    int nr;
-    float us[kMaxNr + 1];   // average launch time per candidate (0: not timed)
+    Shape best;
+    std::vector<std::pair<Shape, float>> tried;   // candidate and its average time in us
 };
 
 std::mutex g_tune_mu;
@@ -492,12 +516,14 @@ void tune_load_locked() {
     while (std::fgets(line, sizeof line, f)) {
         char *bar = std::strrchr(line, '|');
         if (!bar) continue;
-        int nr = 0;
-        if (std::sscanf(bar + 1, " nr=%d", &nr) != 1 || nr < 1 || nr > kMaxNr) continue;
+        Shape sh;
+        if (std::sscanf(bar + 1, " nr=%d chunk=%d", &sh.nr, &sh.chunk) != 2 || sh.nr < 1 ||
+            sh.nr > kMaxNr || sh.chunk < 1)
+            continue;
         std::string key(line, bar - line);
         while (!key.empty() && key.back() == ' ') key.pop_back();
-        TuneEntry e{};
-        e.nr = nr;
+        TuneEntry e;
+        e.best = sh;
         g_tune[key] = e;
     }
     std::fclose(f);
@@ -508,7 +534,7 @@ void tune_store_locked(const std::string &key, const TuneEntry &e) {
     const char *path = std::getenv("WL_TUNE_FILE");
     if (!path) return;
     if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s | nr=%d\n", key.c_str(), e.nr);
+        std::fprintf(f, "%s | nr=%d chunk=%d\n", key.c_str(), e.best.nr, e.best.chunk);
         std::fclose(f);
     }
 }
@@ -524,84 +550,93 @@ std::string tuning_report() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::string out;
     for (const auto &kv : g_tune) {
-        char buf[64];
+        char buf[96];
         out += kv.first;
-        std::snprintf(buf, sizeof buf, " | nr=%d", kv.second.nr);
+        std::snprintf(buf, sizeof buf, " | nr=%d chunk=%d", kv.second.best.nr,
+                      kv.second.best.chunk);
         out += buf;
-        for (int n = 1; n <= kMaxNr; ++n)
-            if (kv.second.us[n] > 0) {
-                std::snprintf(buf, sizeof buf, " t%d=%.1fus", n, kv.second.us[n]);
-                out += buf;
-            }
+        for (const auto &t : kv.second.tried) {
+            std::snprintf(buf, sizeof buf, " [%d,%d]=%.1fus", t.first.nr,
+                          std::min(t.first.chunk, 1 << 20), t.second);
+            out += buf;
+        }
         out += "\n";
     }
     return out;
 }
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
-                               bool link12, hipStream_t s) {
-    constexpr int kDefaultNr = std::is_same<ST, double>::value ? 2 : 4;
-    if (!blocked_ok<ST, RED>() || a.nrhs < 2 || a.gtab) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, 1, s);
+static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12, hipStream_t s) {
+    const Shape kDefault{std::is_same<ST, double>::value ? 2 : 1, 1};
+    if (!blocked_ok<ST, RED>() || a.nrhs < 2 || a.gtab)
+        return launch_nr<ST, NCL, DAG, XPAY, RED>(a, Shape{}, s);
     const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, it->second.nr, s);
+        if (it != g_tune.end()) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, it->second.best, s);
     }
     // is it safe to time the candidates on this call?
     bool safe = tuning_enabled();
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (safe && (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone))
         safe = false;
-    for (int q = 0; q < 2 && safe; ++q) {
+    for (int q = 0; q < a.npar && safe; ++q) {
         const int po = a.first_par ^ q;
-        if (q >= a.npar) break;
         const void *o = a.out[po];
-        if (o == a.in[1 - po] || o == a.xs[po] || o == a.aux[po] || o == a.in[po]) safe = false;
+        if (o == a.in[0] || o == a.in[1] || o == a.xs[po] || o == a.aux[po]) safe = false;
     }
-    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, kDefaultNr, s);
+    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, kDefault, s);
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    TuneEntry best{};
-    best.nr = kDefaultNr;
+    TuneEntry ent;
+    ent.best = kDefault;
     float best_t = 1e30f;
-    constexpr int kReps = 3;
-    for (int nr = 1; nr <= kMaxNr && err == hipSuccess; ++nr) {
-        if (nr > a.nrhs) break;
-        err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, nr, s);   // warm-up
+    auto trial = [&](Shape sh) {
+        constexpr int kReps = 3;
+        err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);   // warm-up
         if (err == hipSuccess) err = hipEventRecord(e0, s);
         for (int k = 0; k < kReps && err == hipSuccess; ++k)
-            err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, nr, s);
+            err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) break;
-        best.us[nr] = 1e3f * ms / kReps;
-        if (best.us[nr] < best_t) {
-            best_t = best.us[nr];
-            best.nr = nr;
+        if (err != hipSuccess) return;
+        const float us = 1e3f * ms / kReps;
+        ent.tried.push_back({sh, us});
+        if (us < best_t) {
+            best_t = us;
+            ent.best = sh;
         }
+    };
+    for (int nr = 1; nr <= kMaxNr && nr <= a.nrhs && err == hipSuccess; ++nr) trial(Shape{nr, 1});
+    const int nr = ent.best.nr;
+    const int ngroups = (a.nrhs + nr - 1) / nr;
+    for (int c : kChunks) {
+        if (err != hipSuccess || ngroups < 2) break;
+        if (c == 1) continue;
+        if (c >= a.nb_rhs && c != kChunks[sizeof kChunks / sizeof kChunks[0] - 1]) continue;
+        trial(Shape{nr, c});
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (err != hipSuccess) return err;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store_locked(key, best);
+        tune_store_locked(key, ent);
     }
-    // leave the chosen variant's result in place
-    return launch_nr<ST, NCL, DAG, XPAY, RED>(a, best.nr, s);
+    // leave the chosen shape's result in place
+    return launch_nr<ST, NCL, DAG, XPAY, RED>(a, ent.best, s);
 }
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
 static hipError_t launch_t(const HopArgs<Real<ST>> &a, const HopCall &call, int prec, bool link12,
                            hipStream_t s) {
-    const hipError_t e = launch_tuned<ST, NCL, DAG, XPAY, RED>(a, call, prec, link12, s);
+    const hipError_t e = launch_tuned<ST, NCL, DAG, XPAY, RED>(a, prec, link12, s);
     if (e != hipSuccess || RED == kRedNone) return e;
     constexpr int NS = RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3);
     return launch_finish(a.red, NS, a.nb_rhs, a.nrhs, a.skip, s);
@@ -649,6 +684,7 @@ static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Pha
     a.nrhs = call.nrhs < 1 ? 1 : call.nrhs;
     a.nb_rhs = g.bpp * call.npar;
     a.ngroups = a.nrhs;
+    a.chunk = 1;
     a.nblocks = a.nb_rhs * a.nrhs;
     a.fstride = call.fstride;
     a.c = R(call.c);
