@@ -235,6 +235,13 @@ int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], do
                       int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream);
 
+/* Streaming device-to-device copy of `bytes` bytes (both pointers 16-byte
+ * aligned, bytes a multiple of 16; the buffers must not overlap), loads then
+ * non-temporal stores, 64 bytes per thread: the achievable-bandwidth
+ * reference the operator kernels are measured against. Asynchronous on
+ * `stream`. WL_EINVAL on misaligned or overlapping arguments. */
+int wl_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Autotuning record. Batched operator launches (wilson_dslash_batch and the
  * batched solves) give each thread several right-hand sides at once, so one
  * link load serves all of them; the first launch of each shape (precision,

@@ -442,6 +442,15 @@ int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims
                         work_bytes, stats, stream);
 }
 
+int wl_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(WL_EINVAL, "NULL buffer");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    if ((a | b | bytes) & 15) return fail(WL_EINVAL, "pointers and size must be multiples of 16");
+    if (a < b + bytes && b < a + bytes) return fail(WL_EINVAL, "src and dst overlap");
+    const hipError_t e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_stream_copy");
+}
+
 size_t wl_tuning_report(char *buf, size_t len) {
     const std::string r = tuning_report();
     if (buf && len > 0) {

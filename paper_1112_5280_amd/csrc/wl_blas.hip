@@ -512,4 +512,38 @@ hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Streaming copy: the achievable-bandwidth reference. Each thread moves
+// kCopyVec 16-byte vectors, loads first, then non-temporal stores.
+// ---------------------------------------------------------------------------
+constexpr int kCopyVec = 4;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kBlock) stream_copy_kernel(const u32x4 *src, u32x4 *dst,
+                                                             size_t n) {
+    const size_t base = (size_t(blockIdx.x) * kBlock * kCopyVec) + threadIdx.x;
+    u32x4 v[kCopyVec];
+#pragma unroll
+    for (int k = 0; k < kCopyVec; ++k) {
+        const size_t j = base + size_t(k) * kBlock;
+        if (j < n) v[k] = __builtin_nontemporal_load(&src[j]);
+    }
+#pragma unroll
+    for (int k = 0; k < kCopyVec; ++k) {
+        const size_t j = base + size_t(k) * kBlock;
+        if (j < n) __builtin_nontemporal_store(v[k], &dst[j]);
+    }
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const size_t per = size_t(kBlock) * kCopyVec;
+    const size_t blocks = (n + per - 1) / per;
+    if (blocks > 0x7fffffffUL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                       static_cast<const u32x4 *>(src), static_cast<u32x4 *>(dst), n);
+    return hipGetLastError();
+}
+
 }  // namespace wl

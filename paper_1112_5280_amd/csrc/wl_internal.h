@@ -287,6 +287,8 @@ struct HopCall {
 };
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s);
+// Device copy of bytes (a multiple of 16, 16-byte aligned) with streaming stores
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // The autotuner's choices so far, one line per tuned batched-operator shape.
 std::string tuning_report();
 

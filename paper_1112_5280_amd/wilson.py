@@ -47,7 +47,7 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch",
            "wl_problems_workspace_bytes", "solve_cg_problems",
            "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
-           "wl_server_pending", "wl_server_destroy", "wl_tuning_report")
+           "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy")
 
 
 class WilsonError(RuntimeError):
@@ -134,6 +134,8 @@ def _load():
     lib.wl_server_destroy.restype = ctypes.c_int
     lib.wl_tuning_report.argtypes = [ctypes.c_char_p, SZ]
     lib.wl_tuning_report.restype = SZ
+    lib.wl_stream_copy.argtypes = [P, P, SZ, P]
+    lib.wl_stream_copy.restype = ctypes.c_int
     return lib
 
 
@@ -389,6 +391,12 @@ def solve_cg_problems(problems, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000
         d["status_name"] = STATUS_NAMES.get(d["status"], "?")
         out.append(d)
     return code, out
+
+
+def stream_copy(src, dst, nbytes=None, stream=None):
+    """Streaming device copy (the achievable-bandwidth reference)."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    _check(lib.wl_stream_copy(_ptr(src), _ptr(dst), n, _stream(stream)), "wl_stream_copy")
 
 
 def tuning_report():

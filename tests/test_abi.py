@@ -147,3 +147,12 @@ def test_server_config_checks(w):
     assert w.lib.wl_server_next(None, ctypes.byref(t), None, None) == -1
     assert w.lib.wl_server_pending(None) == 0
     assert w.lib.wl_server_destroy(None) == 0
+
+
+def test_stream_copy_checks(w):
+    lib = w.lib
+    assert lib.wl_stream_copy(None, _p(4096), 64, None) == -1
+    assert lib.wl_stream_copy(_p(4096), _p(8192), 65, None) == -1       # size not a multiple of 16
+    assert lib.wl_stream_copy(_p(4104), _p(8192), 64, None) == -1       # misaligned
+    assert lib.wl_stream_copy(_p(4096), _p(4096 + 32), 64, None) == -1  # overlap
+    assert "overlap" in w.last_error()

@@ -141,3 +141,13 @@ def test_register_blocked_batches_equal_single(w, nrhs, flags):
                               gu.to_np(w.unpack_spinor(one, dims, prec))), r
     rep = w.tuning_report()
     assert "nrhs=%d " % nrhs in rep and "L=4x6x4x8" in rep, rep
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096, 16 * 1023, (1 << 20) + 48])
+def test_stream_copy(w, nbytes):
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes + 256, dtype=torch.uint8, device="cuda")
+    w.stream_copy(src, dst, nbytes)
+    gu.sync()
+    assert torch.equal(dst[:nbytes], src)
+    assert not dst[nbytes:].any()              # nothing written past the end

@@ -1,0 +1,68 @@
+"""Solves at the benchmark's full sizes, each solution checked by the CPU
+oracle's FP64 residual (one oracle operator apply per solution).
+
+* 32^3 x 64, exp(i 0.35 H) links, kappa = 0.155, Gaussian source: the
+  even-odd mixed-precision CG the benchmark times (FP32 inner and FP16-storage
+  inner), and the plain FP64 solve; the mixed solutions agree with the FP64
+  one within the conditioning bound.
+* 24^3 x 48, exp(i 0.3 H), kappa = 0.15: the 12 spin-colour point sources of
+  one site solved as one batch.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_5280_amd import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_1112_5280_amd import wilson
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return wilson
+
+
+def test_mixed_solves_32x64(w):
+    dims, kappa = (32, 32, 32, 64), 0.155
+    U = synth.gauge_smooth(dims, 0.35, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    xs = {}
+    for flags, name in ((0x20 | 0x40, "mixed-f32"), (0x20 | 0x40 | 0x2, "mixed-f16"),
+                        (0x20, "f64")):
+        st = w.solve_cg(G, B, X, dims, kappa, maxiter=20000, flags=flags)
+        assert st["status"] == 0, (name, st)
+        x = gu.to_np(w.unpack_spinor(X, dims))
+        res = oracle.true_residual(U, b, x, dims, kappa)
+        assert res <= 1e-10, (name, res)
+        xs[name] = x
+    # two solutions with residual <= 1e-10 differ by at most cond(M) * 2e-10;
+    # here they agree far better than that
+    for name in ("mixed-f32", "mixed-f16"):
+        d = np.linalg.norm(xs[name] - xs["f64"]) / np.linalg.norm(xs["f64"])
+        assert d < 1e-7, (name, d)
+
+
+def test_point_source_batch_24x48(w):
+    dims, kappa = (24, 24, 24, 48), 0.15
+    U = synth.gauge_smooth(dims, 0.30, 0)
+    site = synth.random_site(dims, 2)
+    n = 12
+    G = w.pack_gauge(U, dims)
+    B = w.empty_batch(dims, n)
+    srcs = []
+    for r in range(n):
+        srcs.append(synth.point_source(dims, site, r // 3, r % 3))
+        w.batch_field(B, dims, 0, r).copy_(w.pack_spinor(srcs[-1], dims))
+    X = w.empty_batch(dims, n)
+    code, stats = w.solve_cg_batch(G, B, X, n, dims, kappa, maxiter=20000, flags=0x20 | 0x100)
+    assert code == 0, stats
+    for r in range(n):
+        x = gu.to_np(w.unpack_spinor(w.batch_field(X, dims, 0, r), dims))
+        assert oracle.true_residual(U, srcs[r], x, dims, kappa) <= 1e-10, r
