@@ -85,6 +85,8 @@ struct HopArgs {
     int nb_rhs;            // blocks per right-hand side
     int ngroups;           // RHS groups (NR right-hand sides per thread)
     int chunk;             // site blocks per chunk of the block order
+    int tgroup;            // slice tiles walked through time together (0: off)
+    int ntile_t;           // blocks per time slice (0 when a slice is not whole blocks)
     int nrhs;              // right-hand sides (fields fstride bytes apart)
     size_t fstride;
     R c;
@@ -306,14 +308,30 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
             c[r] = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
         }
     }
-    int pidx, bi;
+    int pidx, bo;   // output parity, position of the block in its parity's order
     if (WL_PAR_INTERLEAVE && a.npar == 2) {
         pidx = b & 1;
-        bi = b >> 1;
+        bo = b >> 1;
     } else {
         pidx = b >= g.bpp ? 1 : 0;
-        bi = b - pidx * g.bpp;
+        bo = b - pidx * g.bpp;
     }
+    // position -> lexicographic site block bi. With tile groups (time slices
+    // of a whole number of blocks), the blocks walk every time slice of
+    // `tgroup` slice tiles before the next tiles: a neighbour slice is then
+    // reused a few blocks later instead of a whole slice later. The partial
+    // slot stays the lexicographic one, so reductions keep their bits.
+    int bi = bo;
+    if (a.tgroup > 0 && a.tgroup < a.ntile_t) {
+        const int Lt = g.L[3];
+        const int span = a.tgroup * Lt;
+        const int grp = bo / span;
+        const int g0 = grp * a.tgroup;
+        const int gg = min(a.tgroup, a.ntile_t - g0);
+        const int rem = bo - grp * span;
+        bi = (rem / gg) * a.ntile_t + g0 + rem % gg;
+    }
+    const int slot = (WL_PAR_INTERLEAVE && a.npar == 2) ? 2 * bi + pidx : pidx * g.bpp + bi;
     const int p = a.first_par ^ pidx;
     const int i = bi * kBlock + threadIdx.x;
 
@@ -427,9 +445,9 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
     }
     if constexpr (RED != kRedNone) {
         if constexpr (NR == 1)
-            block_partial<NS>(sums[0], rhs_reduce(a.red, rhs0, a.nb_rhs).partials, b, a.nb_rhs);
+            block_partial<NS>(sums[0], rhs_reduce(a.red, rhs0, a.nb_rhs).partials, slot, a.nb_rhs);
         else
-            block_partial_rhs<NS, NR>(sums, on, a.red, rhs0, b, a.nb_rhs);
+            block_partial_rhs<NS, NR>(sums, on, a.red, rhs0, slot, a.nb_rhs);
     }
 }
 
@@ -438,10 +456,11 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
 // ---------------------------------------------------------------------------
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
-static hipError_t launch_kernel(HopArgs<Real<ST>> a, int chunk, hipStream_t s) {
+static hipError_t launch_kernel(HopArgs<Real<ST>> a, int chunk, int tgroup, hipStream_t s) {
     a.ngroups = (a.nrhs + NR - 1) / NR;
     a.nblocks = a.nb_rhs * a.ngroups;
     a.chunk = std::max(1, std::min(chunk, a.nb_rhs));
+    a.tgroup = tgroup;
     hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED, NR>), dim3(a.nblocks), dim3(kBlock),
                        0, s, a);
     return hipGetLastError();
@@ -455,36 +474,39 @@ constexpr bool blocked_ok() {
     return !std::is_same<ST, Half>::value && (RED == kRedNone || RED == kRedNorm);
 }
 
-// A launch shape of a batched operator: RHS per thread, site blocks per chunk.
+// A launch shape: RHS per thread, site blocks per chunk (batches), slice
+// tiles per time walk (0: lexicographic order).
 struct Shape {
-    int nr = 1, chunk = 1;
+    int nr = 1, chunk = 1, tg = 0;
 };
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
 static hipError_t launch_nr(const HopArgs<Real<ST>> &a, Shape sh, hipStream_t s) {
     if constexpr (blocked_ok<ST, RED>()) {
         switch (sh.nr) {
-        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, sh.chunk, s);
-        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, sh.chunk, s);
-        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, sh.chunk, s);
+        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, sh.chunk, sh.tg, s);
+        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, sh.chunk, sh.tg, s);
+        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, sh.chunk, sh.tg, s);
         default: break;
         }
     }
-    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, sh.chunk, s);
+    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, sh.chunk, sh.tg, s);
 }
 
 // ---- autotuning of batched launch shapes -----------------------------------
-// The first batched launch of each shape key (precision, links, operator,
+// The first launch of each shape key (precision, links, operator,
 // reduction, batch size, lattice) times candidate launch shapes on the call's
 // own buffers, when that is safe (no graph capture under way, the output
 // aliases no input: the kernel is then idempotent and every candidate writes
-// the same bits), and keeps the fastest: first the RHS-per-thread count with
-// chunk 1, then chunk lengths for that count. Choices are cached per process
-// and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables tuning (fixed
-// default shape).
+// the same bits), and keeps the fastest: first the RHS-per-thread count, then
+// the tile group of the time walk, then the chunk length. Choices are cached
+// per process and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables
+// tuning (fixed default shape); WL_TUNE_FORCE="nr,chunk,tg" imposes a shape
+// (where it applies) on every launch.
 namespace {
 
 constexpr int kChunks[] = {1, 4, 16, 64, 1 << 30};
+constexpr int kTileGroups[] = {1, 2, 4, 8, 16, 32};
 
 struct TuneEntry {
     Shape best;
@@ -517,8 +539,8 @@ void tune_load_locked() {
         char *bar = std::strrchr(line, '|');
         if (!bar) continue;
         Shape sh;
-        if (std::sscanf(bar + 1, " nr=%d chunk=%d", &sh.nr, &sh.chunk) != 2 || sh.nr < 1 ||
-            sh.nr > kMaxNr || sh.chunk < 1)
+        if (std::sscanf(bar + 1, " nr=%d chunk=%d tg=%d", &sh.nr, &sh.chunk, &sh.tg) != 3 ||
+            sh.nr < 1 || sh.nr > kMaxNr || sh.chunk < 1 || sh.tg < 0)
             continue;
         std::string key(line, bar - line);
         while (!key.empty() && key.back() == ' ') key.pop_back();
@@ -534,7 +556,8 @@ void tune_store_locked(const std::string &key, const TuneEntry &e) {
     const char *path = std::getenv("WL_TUNE_FILE");
     if (!path) return;
     if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s | nr=%d chunk=%d\n", key.c_str(), e.best.nr, e.best.chunk);
+        std::fprintf(f, "%s | nr=%d chunk=%d tg=%d\n", key.c_str(), e.best.nr, e.best.chunk,
+                     e.best.tg);
         std::fclose(f);
     }
 }
@@ -552,12 +575,12 @@ std::string tuning_report() {
     for (const auto &kv : g_tune) {
         char buf[96];
         out += kv.first;
-        std::snprintf(buf, sizeof buf, " | nr=%d chunk=%d", kv.second.best.nr,
-                      kv.second.best.chunk);
+        std::snprintf(buf, sizeof buf, " | nr=%d chunk=%d tg=%d", kv.second.best.nr,
+                      std::min(kv.second.best.chunk, 1 << 20), kv.second.best.tg);
         out += buf;
         for (const auto &t : kv.second.tried) {
-            std::snprintf(buf, sizeof buf, " [%d,%d]=%.1fus", t.first.nr,
-                          std::min(t.first.chunk, 1 << 20), t.second);
+            std::snprintf(buf, sizeof buf, " [%d,%d,%d]=%.1fus", t.first.nr,
+                          std::min(t.first.chunk, 1 << 20), t.first.tg, t.second);
             out += buf;
         }
         out += "\n";
@@ -567,9 +590,20 @@ std::string tuning_report() {
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
 static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12, hipStream_t s) {
-    const Shape kDefault{std::is_same<ST, double>::value ? 2 : 1, 1};
-    if (!blocked_ok<ST, RED>() || a.nrhs < 2 || a.gtab)
-        return launch_nr<ST, NCL, DAG, XPAY, RED>(a, Shape{}, s);
+    const bool can_nr = blocked_ok<ST, RED>() && a.nrhs >= 2 && !a.gtab;
+    const bool can_tg = a.ntile_t > 1;
+    Shape def;
+    if (can_nr && std::is_same<ST, double>::value) def.nr = 2;
+    if (const char *f = std::getenv("WL_TUNE_FORCE")) {   // fixed shape (testing)
+        Shape sh;
+        if (std::sscanf(f, "%d,%d,%d", &sh.nr, &sh.chunk, &sh.tg) == 3) {
+            sh.nr = can_nr ? std::max(1, std::min(sh.nr, kMaxNr)) : 1;
+            sh.chunk = std::max(1, sh.chunk);
+            if (sh.tg < 0 || sh.tg >= a.ntile_t) sh.tg = 0;
+            return launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);
+        }
+    }
+    if (!can_nr && !can_tg) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
     const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -587,15 +621,16 @@ static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12
         const void *o = a.out[po];
         if (o == a.in[0] || o == a.in[1] || o == a.xs[po] || o == a.aux[po]) safe = false;
     }
-    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, kDefault, s);
+    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
     TuneEntry ent;
-    ent.best = kDefault;
+    ent.best = def;
     float best_t = 1e30f;
     auto trial = [&](Shape sh) {
+        if (err != hipSuccess) return;
         constexpr int kReps = 3;
         err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);   // warm-up
         if (err == hipSuccess) err = hipEventRecord(e0, s);
@@ -613,14 +648,28 @@ static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12
             ent.best = sh;
         }
     };
-    for (int nr = 1; nr <= kMaxNr && nr <= a.nrhs && err == hipSuccess; ++nr) trial(Shape{nr, 1});
-    const int nr = ent.best.nr;
-    const int ngroups = (a.nrhs + nr - 1) / nr;
-    for (int c : kChunks) {
-        if (err != hipSuccess || ngroups < 2) break;
-        if (c == 1) continue;
-        if (c >= a.nb_rhs && c != kChunks[sizeof kChunks / sizeof kChunks[0] - 1]) continue;
-        trial(Shape{nr, c});
+    // 1: right-hand sides per thread (lexicographic order, chunk 1)
+    if (can_nr) {
+        for (int nr = 1; nr <= kMaxNr && nr <= a.nrhs; ++nr) trial(Shape{nr, 1, 0});
+    } else {
+        trial(Shape{1, 1, 0});
+    }
+    // 2: slice tiles walked through time together
+    if (can_tg) {
+        const Shape b1 = ent.best;
+        for (int tg : kTileGroups)
+            if (tg < a.ntile_t) trial(Shape{b1.nr, 1, tg});
+    }
+    // 3: chunks of the RHS-group order
+    {
+        const Shape b2 = ent.best;
+        const int ngroups = (a.nrhs + b2.nr - 1) / b2.nr;
+        if (ngroups >= 2)
+            for (int c : kChunks) {
+                if (c == 1) continue;
+                if (c >= a.nb_rhs && c != kChunks[sizeof kChunks / sizeof kChunks[0] - 1]) continue;
+                trial(Shape{b2.nr, c, b2.tg});
+            }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -685,6 +734,11 @@ static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Pha
     a.nb_rhs = g.bpp * call.npar;
     a.ngroups = a.nrhs;
     a.chunk = 1;
+    a.tgroup = 0;
+    {
+        const int A = g.Lxh * g.L[1] * g.L[2];
+        a.ntile_t = A % kBlock == 0 ? A / kBlock : 0;
+    }
     a.nblocks = a.nb_rhs * a.nrhs;
     a.fstride = call.fstride;
     a.c = R(call.c);
