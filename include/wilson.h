@@ -43,9 +43,10 @@
  *     checkerboard index of x. 18-real: the 9 complex entries, row-major;
  *     12-real (WL_LINK12): rows 0 and 1 only, row 2 = conj(row0 x row1) is
  *     rebuilt in the kernel (exact for det U = 1). FP64: one complex per
- *     double2 chunk; FP32: float2 per complex (18-real), float4 per complex
- *     pair (12-real); FP16: binary16 pairs per complex (18-real) or quads
- *     per complex pair (12-real), unscaled (|U_ij| <= 1).
+ *     double2 chunk; FP32: float4 chunks of two complex, and for 18-real a
+ *     last float2 chunk with the ninth; FP16 (unscaled, |U_ij| <= 1): chunks
+ *     of four complex (8 binary16), then the rest in one narrower chunk
+ *     (18-real: 2 chunks + one complex; 12-real: 1 chunk + two complex).
  *   Checkerboard index of site s (with parity (x+y+z+t) & 1) is s / 2.
  *   Padding entries (checkerboard index >= Vh) are never read or written by
  *   the operators.

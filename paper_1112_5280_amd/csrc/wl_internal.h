@@ -106,22 +106,36 @@ template <> struct Vec<Half, 4> { typedef h8v T; };
 // complex numbers per chunk: 16-byte chunks for spinors where possible
 template <typename ST> constexpr int spinor_cw() { return 16 / cbytes<ST>(); }
 // links: two complex per chunk for 12-real FP32/FP16 storage, else one (9 is odd)
+// links: 16-byte chunks where possible (FP32 two complex, FP16 four), the
+// NCL % cw complex numbers left over in one narrower tail chunk
 template <typename ST, int NCL> constexpr int link_cw() {
-    return (std::is_same<ST, double>::value || NCL == 9) ? 1 : 2;
+    return std::is_same<ST, double>::value ? 1 : (std::is_same<ST, float>::value ? 2 : 4);
 }
 
+// NC complex numbers of site i: NC / CW arrays of S chunks of CW complex, then
+// (if NC % CW != 0) one array of S chunks holding the remaining NC % CW.
 template <typename ST, int NC, int CW>
 __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Real<ST>> *v) {
     using T = typename Vec<ST, CW>::T;
     using R = Real<ST>;
+    constexpr int NF = NC / CW, TL = NC % CW;
     const T *p = static_cast<const T *>(base);
 #pragma unroll
-    for (int j = 0; j < NC / CW; ++j) {
+    for (int j = 0; j < NF; ++j) {
         const T c = p[j * S + i];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             v[CW * j + k].re = R(c[2 * k]);
             v[CW * j + k].im = R(c[2 * k + 1]);
+        }
+    }
+    if constexpr (TL > 0) {
+        using TT = typename Vec<ST, TL>::T;
+        const TT c = reinterpret_cast<const TT *>(p + size_t(NF) * S)[i];
+#pragma unroll
+        for (int k = 0; k < TL; ++k) {
+            v[CW * NF + k].re = R(c[2 * k]);
+            v[CW * NF + k].im = R(c[2 * k + 1]);
         }
     }
 }
@@ -134,9 +148,10 @@ __device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<R
                                            Real<ST> scale = Real<ST>(1)) {
     using T = typename Vec<ST, CW>::T;
     using E = typename Elem<ST>::T;
+    constexpr int NF = NC / CW, TL = NC % CW;
     T *p = static_cast<T *>(base);
 #pragma unroll
-    for (int j = 0; j < NC / CW; ++j) {
+    for (int j = 0; j < NF; ++j) {
         T c;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
@@ -145,6 +160,18 @@ __device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<R
         }
         if constexpr (NT) __builtin_nontemporal_store(c, &p[j * S + i]);
         else p[j * S + i] = c;
+    }
+    if constexpr (TL > 0) {
+        using TT = typename Vec<ST, TL>::T;
+        TT c;
+#pragma unroll
+        for (int k = 0; k < TL; ++k) {
+            c[2 * k] = static_cast<E>(v[CW * NF + k].re * scale);
+            c[2 * k + 1] = static_cast<E>(v[CW * NF + k].im * scale);
+        }
+        TT *q = reinterpret_cast<TT *>(p + size_t(NF) * S) + i;
+        if constexpr (NT) __builtin_nontemporal_store(c, q);
+        else *q = c;
     }
 }
 
