@@ -70,7 +70,7 @@ def log(*a):
 
 
 # the sources that define the hopping kernels (their code, layout and reductions)
-HOP_SOURCES = ("wl_dslash.hip", "wl_internal.h", "wl_reduce.h")
+HOP_SOURCES = ("wl_hop.h", "wl_hop_f32.hip", "wl_dslash.hip", "wl_internal.h", "wl_reduce.h")
 
 
 def kernel_source_hash():

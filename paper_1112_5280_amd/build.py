@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwilson.so")
 
-SOURCES = ["wl_api.hip", "wl_dslash.hip", "wl_blas.hip", "wl_solver.hip", "wl_server.hip"]
+SOURCES = ["wl_api.hip", "wl_dslash.hip", "wl_hop_f64.hip", "wl_hop_f32.hip", "wl_hop_f16.hip",
+           "wl_blas.hip", "wl_solver.hip", "wl_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = [
@@ -48,7 +49,7 @@ def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
     build_dir = BUILD if not defines else os.path.join(
         BUILD, "v_" + "_".join(d.replace("=", "") for d in defines))
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, defines, build_dir), SOURCES))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]

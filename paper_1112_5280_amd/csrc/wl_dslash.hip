@@ -1,531 +1,15 @@
-// wl_dslash.hip -- the Wilson hopping term on the even-odd layout.
-//
-// One thread computes one output site x of parity p:
-//
-//   out(x) = xs(x) + c * sum_mu [ f (1 -/+ gamma_mu) U_mu(x)        psi(x+mu)
-//                               + b (1 +/- gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
-//
-// (paper Sec. 3: the "dslash", the non-diagonal part of the fermion matrix; the
-// upper signs are D_W, the lower ones its gamma_5 conjugate D_W^dag). All eight
-// neighbours have parity 1-p. Each hop first projects the neighbour spinor to
-// a half spinor (two colour vectors), multiplies both by the link (or its
-// adjoint), multiplies by the boundary phase when the hop wraps, and expands
-// back to four spins while accumulating. Spin projection in the chiral basis
-// gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_t = [[0, 1], [1, 0]]:
-//   (1 + s gamma_mu) psi = (h0, h1, lower)   with, for s = +-1,
-//   mu=x: h = (psi0 - s i psi3, psi1 - s i psi2), lower = (s i h1, s i h0)
-//   mu=y: h = (psi0 - s psi3,   psi1 + s psi2),   lower = (s h1, -s h0)
-//   mu=z: h = (psi0 - s i psi2, psi1 + s i psi3), lower = (s i h0, -s i h1)
-//   mu=t: h = (psi0 + s psi2,   psi1 + s psi3),   lower = (s h0, s h1)
-// Links are stored as 18 reals, or as rows 0 and 1 (12 reals) with row 2
-// rebuilt as conj(row0 x row1); phases are applied after the rebuild.
-// Storage is FP64, FP32 or FP16 (spinors with a per-site scale); arithmetic
-// is FP64 for FP64 storage and FP32 otherwise.
-//
-// With batches of fields, a thread may own several right-hand sides (NR),
-// which then share every link load.
-//
-// Model cost: 1320 flop per output site for the hopping term, +48 for the
-// xpay; compulsory bytes: 8 links and 8 neighbour spinors amortised over the
-// lattice (see the layout notes in wilson.h).
-#include <algorithm>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <map>
-#include <mutex>
-#include <string>
-#include <vector>
-
-#include "wl_internal.h"
-#include "wl_reduce.h"
-
-// Launch-shape knobs (compile time). Minimum waves per SIMD the register
-// allocation must allow, per precision; streaming (non-temporal) output
-// stores; XCD-contiguous block order; interleaving the two parities' blocks
-// in full-lattice launches so the blocks that share links run on one XCD.
-#ifndef WL_F64_WAVES
-#define WL_F64_WAVES 1
-#endif
-#ifndef WL_F32_WAVES
-#define WL_F32_WAVES 1
-#endif
-#ifndef WL_NT_STORE
-#define WL_NT_STORE 1
-#endif
-#ifndef WL_XCD_REMAP
-#define WL_XCD_REMAP 1
-#endif
-#ifndef WL_PAR_INTERLEAVE
-#define WL_PAR_INTERLEAVE 1
-#endif
+// wl_dslash.hip -- launch dispatch of the hopping term and the autotuner's
+// shape record (the kernels are in wl_hop.h).
+#include "wl_hop.h"
 
 namespace wl {
 
-constexpr int kMaxNr = 4;   // right-hand sides per thread in batched launches
-
-template <typename ST>
-struct MinWaves {
-    static constexpr int value = std::is_same<ST, double>::value ? WL_F64_WAVES : WL_F32_WAVES;
-};
-
-enum RedMode : int { kRedNone = 0, kRedNorm = 1, kRedDotAux = 2, kRedTS = 3 };
-
-template <typename R>
-struct HopArgs {
-    const void *gauge;     // packed gauge base (parity 0, mu 0, chunk 0)
-    const void *in[2];     // input parity blocks
-    const void *xs[2];     // xpay source parity blocks (or null)
-    const void *aux[2];    // vector for <aux, out> (kRedDotAux)
-    void *out[2];          // output parity blocks
-    Geom g;
-    int first_par;         // parity of the first output block
-    int npar;              // output parities in this launch (1 or 2)
-    int nblocks;           // nb_rhs * ngroups
-    int nb_rhs;            // blocks per right-hand side
-    int ngroups;           // RHS groups (NR right-hand sides per thread)
-    int chunk;             // site blocks per chunk of the block order
-    int tgroup;            // slice tiles walked through time together (0: off)
-    int ntile_t;           // blocks per time slice (0 when a slice is not whole blocks)
-    int nrhs;              // right-hand sides (fields fstride bytes apart)
-    size_t fstride;
-    R c;
-    R phr[4], phi[4];      // boundary phases
-    const int *skip;
-    Reduce red;
-    const void *const *gtab;   // per-RHS gauge fields (or null: `gauge` shared)
-    const Scalars *ksc;        // per-RHS kappa (or null: `c` shared)
-    R cmul;
-    int cpow;
-};
-
-template <int MU, int S, typename R>
-__device__ __forceinline__ void project(const cpx<R> psi[12], cpx<R> h[6]) {
-    // psi[spin*3 + colour]
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cpx<R> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
-        if constexpr (MU == 0) {
-            h[a] = (S > 0) ? p0 - ci(p3) : p0 + ci(p3);
-            h[3 + a] = (S > 0) ? p1 - ci(p2) : p1 + ci(p2);
-        } else if constexpr (MU == 1) {
-            h[a] = (S > 0) ? p0 - p3 : p0 + p3;
-            h[3 + a] = (S > 0) ? p1 + p2 : p1 - p2;
-        } else if constexpr (MU == 2) {
-            h[a] = (S > 0) ? p0 - ci(p2) : p0 + ci(p2);
-            h[3 + a] = (S > 0) ? p1 + ci(p3) : p1 - ci(p3);
-        } else {
-            h[a] = (S > 0) ? p0 + p2 : p0 - p2;
-            h[3 + a] = (S > 0) ? p1 + p3 : p1 - p3;
-        }
-    }
-}
-
-template <int MU, int S, typename R>
-__device__ __forceinline__ void accumulate(cpx<R> acc[12], const cpx<R> u[6]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cpx<R> u0 = u[a], u1 = u[3 + a];
-        acc[a] = acc[a] + u0;
-        acc[3 + a] = acc[3 + a] + u1;
-        if constexpr (MU == 0) {
-            acc[6 + a] = (S > 0) ? acc[6 + a] + ci(u1) : acc[6 + a] - ci(u1);
-            acc[9 + a] = (S > 0) ? acc[9 + a] + ci(u0) : acc[9 + a] - ci(u0);
-        } else if constexpr (MU == 1) {
-            acc[6 + a] = (S > 0) ? acc[6 + a] + u1 : acc[6 + a] - u1;
-            acc[9 + a] = (S > 0) ? acc[9 + a] - u0 : acc[9 + a] + u0;
-        } else if constexpr (MU == 2) {
-            acc[6 + a] = (S > 0) ? acc[6 + a] + ci(u0) : acc[6 + a] - ci(u0);
-            acc[9 + a] = (S > 0) ? acc[9 + a] - ci(u1) : acc[9 + a] + ci(u1);
-        } else {
-            acc[6 + a] = (S > 0) ? acc[6 + a] + u0 : acc[6 + a] - u0;
-            acc[9 + a] = (S > 0) ? acc[9 + a] + u1 : acc[9 + a] - u1;
-        }
-    }
-}
-
-template <typename ST, int NCL>
-__device__ __forceinline__ void load_link(const void *gauge, const Geom &g, int par, int mu,
-                                          int i, cpx<Real<ST>> u[9]) {
-    load_link_raw<ST, NCL>(gauge, g.S, par, mu, i, u);
-    if constexpr (NCL == 6) {
-        u[6] = cconj(u[1] * u[5] - u[2] * u[4]);
-        u[7] = cconj(u[2] * u[3] - u[0] * u[5]);
-        u[8] = cconj(u[0] * u[4] - u[1] * u[3]);
-    }
-}
-
-// u h (forward) on both colour vectors of the half spinor
-template <typename R>
-__device__ __forceinline__ void su3_mul(const cpx<R> u[9], const cpx<R> h[6], cpx<R> o[6]) {
-#pragma unroll
-    for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            o[3 * sp + a] = u[3 * a] * h[3 * sp] + u[3 * a + 1] * h[3 * sp + 1] +
-                            u[3 * a + 2] * h[3 * sp + 2];
-}
-
-// u^dag h (backward)
-template <typename R>
-__device__ __forceinline__ void su3_dag_mul(const cpx<R> u[9], const cpx<R> h[6], cpx<R> o[6]) {
-#pragma unroll
-    for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            o[3 * sp + a] = cmulc(u[a], h[3 * sp]) + cmulc(u[3 + a], h[3 * sp + 1]) +
-                            cmulc(u[6 + a], h[3 * sp + 2]);
-}
-
-template <typename R>
-__device__ __forceinline__ void times_phase(cpx<R> o[6], R pr, R pi) {
-    const cpx<R> ph{pr, pi};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = ph * o[k];
-}
-
-// One hop direction, forward (FWD) or backward, projector sign S, applied to
-// the NR right-hand sides a thread owns: the link is loaded (and for 12-real
-// storage rebuilt) once and multiplies the projected neighbour of every RHS.
-template <typename ST, int NCL, int MU, int S, bool FWD, int NR>
-__device__ __forceinline__ void hop_dir(const HopArgs<Real<ST>> &a, const void *gauge,
-                                        const char *const (&in_blk)[NR], const bool (&on)[NR],
-                                        int p, int i, int nb, bool wrap,
-                                        cpx<Real<ST>> (&acc)[NR][12]) {
-    using R = Real<ST>;
-    cpx<R> u[9];
-    if constexpr (NR == 1) {
-        // one RHS: neighbour spinor first, then the link (the order the
-        // register allocation of the single-field kernels is best with)
-        cpx<R> psi[12];
-        load_spinor<ST>(in_blk[0], a.g.S, nb, psi);
-        cpx<R> h[6];
-        project<MU, S>(psi, h);
-        cpx<R> o[6];
-        if constexpr (FWD) {
-            load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
-            su3_mul(u, h, o);
-            if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
-        } else {
-            load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
-            su3_dag_mul(u, h, o);
-            if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
-        }
-        accumulate<MU, S>(acc[0], o);
-        return;
-    }
-    if constexpr (FWD)
-        load_link<ST, NCL>(gauge, a.g, p, MU, i, u);
-    else
-        load_link<ST, NCL>(gauge, a.g, 1 - p, MU, nb, u);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        if (NR > 1 && !on[r]) continue;
-        cpx<R> psi[12];
-        load_spinor<ST>(in_blk[r], a.g.S, nb, psi);
-        cpx<R> h[6];
-        project<MU, S>(psi, h);
-        cpx<R> o[6];
-        if constexpr (FWD) {
-            su3_mul(u, h, o);
-            if (wrap) times_phase(o, a.phr[MU], a.phi[MU]);
-        } else {
-            su3_dag_mul(u, h, o);
-            if (wrap) times_phase(o, a.phr[MU], -a.phi[MU]);
-        }
-        accumulate<MU, S>(acc[r], o);
-    }
-}
-
-// Block partials of NR right-hand sides at once: the same shuffle tree and
-// wave order as block_partial, so every RHS's partial is bitwise the one a
-// single-RHS launch would store.
-template <int NS, int NR>
-__device__ __forceinline__ void block_partial_rhs(double (&v)[NR][NS], const bool (&on)[NR],
-                                                  const Reduce &red, int rhs0, int slot, int nb) {
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double sh[kWaves][NR][NS];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-#pragma unroll
-            for (int s = 0; s < NS; ++s) v[r][s] += __shfl_xor(v[r][s], off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-#pragma unroll
-            for (int s = 0; s < NS; ++s) sh[wave][r][s] = v[r][s];
-    __syncthreads();
-    const int r = threadIdx.x;
-    if (r < NR && on[r]) {
-        double *partials = rhs_reduce(red, rhs0 + r, nb).partials;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) t += sh[w][r][s];
-            partials[s * nb + slot] = t;
-        }
-    }
-}
-
-// NR right-hand sides per thread (register blocking over the batch). The
-// logical block index runs over chunks of `chunk` consecutive site blocks;
-// inside a chunk, over the RHS groups, and inside a group over the chunk's
-// site blocks. chunk = 1 puts the groups that share a site range (and its
-// links) back to back; a larger chunk keeps the neighbour spinors of one group
-// (the z and t neighbours lie many blocks away) in cache while the next group
-// still finds the chunk's links there. The order changes no arithmetic.
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
-__global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArgs<Real<ST>> a) {
-    using R = Real<ST>;
-    const Geom &g = a.g;
-    const int bl = WL_XCD_REMAP ? xcd_block(blockIdx.x, a.nblocks) : int(blockIdx.x);
-    const int ch = bl / (a.chunk * a.ngroups);
-    const int base = ch * a.chunk;
-    const int cl = min(a.chunk, a.nb_rhs - base);        // site blocks in this chunk
-    const int rem = bl - base * a.ngroups;
-    const int q = rem / cl;
-    const int b = base + rem % cl;
-    const int rhs0 = q * NR;
-    bool on[NR];
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        on[r] = rhs0 + r < a.nrhs && !rhs_skip(a.skip, rhs0 + r);
-        any = any || on[r];
-    }
-    if (!any) return;
-    const void *gauge = a.gtab ? a.gtab[rhs0] : a.gauge;   // gtab only with NR = 1
-    R c[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        c[r] = a.c;
-        if (a.ksc) {
-            const R k = R(a.ksc[rhs0 + r].kappa);
-            c[r] = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
-        }
-    }
-    int pidx, bo;   // output parity, position of the block in its parity's order
-    if (WL_PAR_INTERLEAVE && a.npar == 2) {
-        pidx = b & 1;
-        bo = b >> 1;
-    } else {
-        pidx = b >= g.bpp ? 1 : 0;
-        bo = b - pidx * g.bpp;
-    }
-    // position -> lexicographic site block bi. With tile groups (time slices
-    // of a whole number of blocks), the blocks walk every time slice of
-    // `tgroup` slice tiles before the next tiles: a neighbour slice is then
-    // reused a few blocks later instead of a whole slice later. The partial
-    // slot stays the lexicographic one, so reductions keep their bits.
-    int bi = bo;
-    if (a.tgroup > 0 && a.tgroup < a.ntile_t) {
-        const int Lt = g.L[3];
-        const int span = a.tgroup * Lt;
-        const int grp = bo / span;
-        const int g0 = grp * a.tgroup;
-        const int gg = min(a.tgroup, a.ntile_t - g0);
-        const int rem = bo - grp * span;
-        bi = (rem / gg) * a.ntile_t + g0 + rem % gg;
-    }
-    const int slot = (WL_PAR_INTERLEAVE && a.npar == 2) ? 2 * bi + pidx : pidx * g.bpp + bi;
-    const int p = a.first_par ^ pidx;
-    const int i = bi * kBlock + threadIdx.x;
-
-    constexpr int NS = RED == kRedNone ? 1 : (RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3));
-    double sums[NR][NS];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) sums[r][s] = 0.0;
-
-    if (i < g.Vh) {
-        // coordinates of the output site
-        const int xh = i % g.Lxh;
-        int rr = i / g.Lxh;
-        const int y = rr % g.L[1];
-        rr /= g.L[1];
-        const int z = rr % g.L[2];
-        const int t = rr / g.L[2];
-        const int x = 2 * xh + ((y + z + t + p) & 1);
-
-        size_t fo[NR];
-        const char *in_blk[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            fo[r] = size_t(rhs0 + r) * a.fstride;
-            in_blk[r] = static_cast<const char *>(a.in[1 - p]) + fo[r];
-        }
-        constexpr int SF = DAG ? 1 : -1;   // forward projector 1 + SF gamma
-        constexpr int SB = -SF;            // backward projector 1 + SB gamma
-
-        cpx<R> acc[NR][12];
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-#pragma unroll
-            for (int k = 0; k < 12; ++k) acc[r][k] = {R(0), R(0)};
-
-        {   // x direction: neighbour checkerboard index changes through x/2
-            const int xp = (x + 1 == g.L[0]) ? 0 : x + 1;
-            const int xm = (x == 0) ? g.L[0] - 1 : x - 1;
-            hop_dir<ST, NCL, 0, SF, true, NR>(a, gauge, in_blk, on, p, i, i - xh + (xp >> 1),
-                                              x == g.L[0] - 1, acc);
-            hop_dir<ST, NCL, 0, SB, false, NR>(a, gauge, in_blk, on, p, i, i - xh + (xm >> 1),
-                                               x == 0, acc);
-        }
-        {
-            const int st = g.Lxh;
-            const int span = (g.L[1] - 1) * st;
-            hop_dir<ST, NCL, 1, SF, true, NR>(a, gauge, in_blk, on, p, i,
-                                              y == g.L[1] - 1 ? i - span : i + st,
-                                              y == g.L[1] - 1, acc);
-            hop_dir<ST, NCL, 1, SB, false, NR>(a, gauge, in_blk, on, p, i,
-                                               y == 0 ? i + span : i - st, y == 0, acc);
-        }
-        {
-            const int st = g.Lxh * g.L[1];
-            const int span = (g.L[2] - 1) * st;
-            hop_dir<ST, NCL, 2, SF, true, NR>(a, gauge, in_blk, on, p, i,
-                                              z == g.L[2] - 1 ? i - span : i + st,
-                                              z == g.L[2] - 1, acc);
-            hop_dir<ST, NCL, 2, SB, false, NR>(a, gauge, in_blk, on, p, i,
-                                               z == 0 ? i + span : i - st, z == 0, acc);
-        }
-        {
-            const int st = g.Lxh * g.L[1] * g.L[2];
-            const int span = (g.L[3] - 1) * st;
-            hop_dir<ST, NCL, 3, SF, true, NR>(a, gauge, in_blk, on, p, i,
-                                              t == g.L[3] - 1 ? i - span : i + st,
-                                              t == g.L[3] - 1, acc);
-            hop_dir<ST, NCL, 3, SB, false, NR>(a, gauge, in_blk, on, p, i,
-                                               t == 0 ? i + span : i - st, t == 0, acc);
-        }
-
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (NR > 1 && !on[r]) continue;
-            cpx<R> o[12];
-            cpx<R> xv[12];
-            if constexpr (XPAY) {
-                load_spinor<ST>(static_cast<const char *>(a.xs[p]) + fo[r], g.S, i, xv);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) o[k] = xv[k] + c[r] * acc[r][k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) o[k] = c[r] * acc[r][k];
-            }
-            store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo[r], g.S, i, o);
-
-            double *sm = sums[r];
-            if constexpr (RED == kRedNorm) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k)
-                    sm[0] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
-            } else if constexpr (RED == kRedDotAux) {   // <aux, out>
-                cpx<R> w[12];
-                load_spinor<ST>(static_cast<const char *>(a.aux[p]) + fo[r], g.S, i, w);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    sm[0] += double(w[k].re) * double(o[k].re) + double(w[k].im) * double(o[k].im);
-                    sm[1] += double(w[k].re) * double(o[k].im) - double(w[k].im) * double(o[k].re);
-                }
-            } else if constexpr (RED == kRedTS) {       // <out, xs>, ||out||^2
-                static_assert(XPAY, "kRedTS needs the xpay source");
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    sm[0] += double(o[k].re) * double(xv[k].re) + double(o[k].im) * double(xv[k].im);
-                    sm[1] += double(o[k].re) * double(xv[k].im) - double(o[k].im) * double(xv[k].re);
-                    sm[2] += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
-                }
-            }
-        }
-    }
-    if constexpr (RED != kRedNone) {
-        if constexpr (NR == 1)
-            block_partial<NS>(sums[0], rhs_reduce(a.red, rhs0, a.nb_rhs).partials, slot, a.nb_rhs);
-        else
-            block_partial_rhs<NS, NR>(sums, on, a.red, rhs0, slot, a.nb_rhs);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Launchers
-// ---------------------------------------------------------------------------
-
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED, int NR>
-static hipError_t launch_kernel(HopArgs<Real<ST>> a, int chunk, int tgroup, hipStream_t s) {
-    a.ngroups = (a.nrhs + NR - 1) / NR;
-    a.nblocks = a.nb_rhs * a.ngroups;
-    a.chunk = std::max(1, std::min(chunk, a.nb_rhs));
-    a.tgroup = tgroup;
-    hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED, NR>), dim3(a.nblocks), dim3(kBlock),
-                       0, s, a);
-    return hipGetLastError();
-}
-
-// RHS per thread the kernels are built for (register blocking of batches):
-// FP64 and FP32 storage, no reduction or a norm; FP16 storage and the
-// BiCGStab reductions use one.
-template <typename ST, int RED>
-constexpr bool blocked_ok() {
-    return !std::is_same<ST, Half>::value && (RED == kRedNone || RED == kRedNorm);
-}
-
-// A launch shape: RHS per thread, site blocks per chunk (batches), slice
-// tiles per time walk (0: lexicographic order).
-struct Shape {
-    int nr = 1, chunk = 1, tg = 0;
-};
-
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_nr(const HopArgs<Real<ST>> &a, Shape sh, hipStream_t s) {
-    if constexpr (blocked_ok<ST, RED>()) {
-        switch (sh.nr) {
-        case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, sh.chunk, sh.tg, s);
-        case 3: return launch_kernel<ST, NCL, DAG, XPAY, RED, 3>(a, sh.chunk, sh.tg, s);
-        case 4: return launch_kernel<ST, NCL, DAG, XPAY, RED, 4>(a, sh.chunk, sh.tg, s);
-        default: break;
-        }
-    }
-    return launch_kernel<ST, NCL, DAG, XPAY, RED, 1>(a, sh.chunk, sh.tg, s);
-}
-
-// ---- autotuning of batched launch shapes -----------------------------------
-// The first launch of each shape key (precision, links, operator,
-// reduction, batch size, lattice) times candidate launch shapes on the call's
-// own buffers, when that is safe (no graph capture under way, the output
-// aliases no input: the kernel is then idempotent and every candidate writes
-// the same bits), and keeps the fastest: first the RHS-per-thread count, then
-// the tile group of the time walk, then the chunk length. Choices are cached
-// per process and, with WL_TUNE_FILE set, in that file; WL_TUNE=0 disables
-// tuning (fixed default shape); WL_TUNE_FORCE="nr,chunk,tg" imposes a shape
-// (where it applies) on every launch.
 namespace {
-
-constexpr int kChunks[] = {1, 4, 16, 64, 1 << 30};
-constexpr int kTileGroups[] = {1, 2, 4, 8, 16, 32};
-
-struct TuneEntry {
-    Shape best;
-    std::vector<std::pair<Shape, float>> tried;   // candidate and its average time in us
-};
 
 std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, int red,
-                     int nrhs, int npar) {
-    char k[160];
-    std::snprintf(k, sizeof k, "hop prec=%d link=%d dag=%d xpay=%d red=%d nrhs=%d npar=%d "
-                               "L=%dx%dx%dx%d",
-                  prec, link12 ? 12 : 18, int(dag), int(xpay), red, nrhs, npar, g.L[0], g.L[1],
-                  g.L[2], g.L[3]);
-    return k;
-}
 
 void tune_load_locked() {
     if (g_tune_loaded) return;
@@ -562,12 +46,37 @@ void tune_store_locked(const std::string &key, const TuneEntry &e) {
     }
 }
 
+
+}  // namespace
+
+std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, int red,
+                     int nrhs, int npar) {
+    char k[160];
+    std::snprintf(k, sizeof k, "hop prec=%d link=%d dag=%d xpay=%d red=%d nrhs=%d npar=%d "
+                               "L=%dx%dx%dx%d",
+                  prec, link12 ? 12 : 18, int(dag), int(xpay), red, nrhs, npar, g.L[0], g.L[1],
+                  g.L[2], g.L[3]);
+    return k;
+}
+
 bool tuning_enabled() {
     const char *v = std::getenv("WL_TUNE");
     return !(v && v[0] == '0');
 }
 
-}  // namespace
+bool tune_find(const std::string &key, Shape *best) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *best = it->second.best;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneEntry &e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, e);
+}
 
 std::string tuning_report() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -588,176 +97,6 @@ std::string tuning_report() {
     return out;
 }
 
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12, hipStream_t s) {
-    const bool can_nr = blocked_ok<ST, RED>() && a.nrhs >= 2 && !a.gtab;
-    const bool can_tg = a.ntile_t > 1;
-    Shape def;
-    if (can_nr && std::is_same<ST, double>::value) def.nr = 2;
-    if (const char *f = std::getenv("WL_TUNE_FORCE")) {   // fixed shape (testing)
-        Shape sh;
-        if (std::sscanf(f, "%d,%d,%d", &sh.nr, &sh.chunk, &sh.tg) == 3) {
-            sh.nr = can_nr ? std::max(1, std::min(sh.nr, kMaxNr)) : 1;
-            sh.chunk = std::max(1, sh.chunk);
-            if (sh.tg < 0 || sh.tg >= a.ntile_t) sh.tg = 0;
-            return launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);
-        }
-    }
-    if (!can_nr && !can_tg) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
-    const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar);
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        auto it = g_tune.find(key);
-        if (it != g_tune.end()) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, it->second.best, s);
-    }
-    // is it safe to time the candidates on this call?
-    bool safe = tuning_enabled();
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (safe && (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone))
-        safe = false;
-    for (int q = 0; q < a.npar && safe; ++q) {
-        const int po = a.first_par ^ q;
-        const void *o = a.out[po];
-        if (o == a.in[0] || o == a.in[1] || o == a.xs[po] || o == a.aux[po]) safe = false;
-    }
-    if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
-
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t err = hipEventCreate(&e0);
-    if (err == hipSuccess) err = hipEventCreate(&e1);
-    TuneEntry ent;
-    ent.best = def;
-    float best_t = 1e30f;
-    auto trial = [&](Shape sh) {
-        if (err != hipSuccess) return;
-        constexpr int kReps = 3;
-        err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);   // warm-up
-        if (err == hipSuccess) err = hipEventRecord(e0, s);
-        for (int k = 0; k < kReps && err == hipSuccess; ++k)
-            err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) return;
-        const float us = 1e3f * ms / kReps;
-        ent.tried.push_back({sh, us});
-        if (us < best_t) {
-            best_t = us;
-            ent.best = sh;
-        }
-    };
-    // 1: right-hand sides per thread (lexicographic order, chunk 1)
-    if (can_nr) {
-        for (int nr = 1; nr <= kMaxNr && nr <= a.nrhs; ++nr) trial(Shape{nr, 1, 0});
-    } else {
-        trial(Shape{1, 1, 0});
-    }
-    // 2: slice tiles walked through time together
-    if (can_tg) {
-        const Shape b1 = ent.best;
-        for (int tg : kTileGroups)
-            if (tg < a.ntile_t) trial(Shape{b1.nr, 1, tg});
-    }
-    // 3: chunks of the RHS-group order
-    {
-        const Shape b2 = ent.best;
-        const int ngroups = (a.nrhs + b2.nr - 1) / b2.nr;
-        if (ngroups >= 2)
-            for (int c : kChunks) {
-                if (c == 1) continue;
-                if (c >= a.nb_rhs && c != kChunks[sizeof kChunks / sizeof kChunks[0] - 1]) continue;
-                trial(Shape{b2.nr, c, b2.tg});
-            }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (err != hipSuccess) return err;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store_locked(key, ent);
-    }
-    // leave the chosen shape's result in place
-    return launch_nr<ST, NCL, DAG, XPAY, RED>(a, ent.best, s);
-}
-
-template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
-static hipError_t launch_t(const HopArgs<Real<ST>> &a, const HopCall &call, int prec, bool link12,
-                           hipStream_t s) {
-    const hipError_t e = launch_tuned<ST, NCL, DAG, XPAY, RED>(a, prec, link12, s);
-    if (e != hipSuccess || RED == kRedNone) return e;
-    constexpr int NS = RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3);
-    return launch_finish(a.red, NS, a.nb_rhs, a.nrhs, a.skip, s);
-}
-
-template <typename ST, int NCL, bool DAG, bool XPAY>
-static hipError_t launch_red(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
-                             bool link12, int red, hipStream_t s) {
-    switch (red) {
-    case kRedNone: return launch_t<ST, NCL, DAG, XPAY, kRedNone>(a, call, prec, link12, s);
-    case kRedNorm: return launch_t<ST, NCL, DAG, XPAY, kRedNorm>(a, call, prec, link12, s);
-    case kRedDotAux: return launch_t<ST, NCL, DAG, XPAY, kRedDotAux>(a, call, prec, link12, s);
-    default:
-        if constexpr (XPAY) return launch_t<ST, NCL, DAG, XPAY, kRedTS>(a, call, prec, link12, s);
-        return hipErrorInvalidValue;
-    }
-}
-
-template <typename ST, int NCL>
-static hipError_t launch_ncl(const HopArgs<Real<ST>> &a, const HopCall &call, int prec,
-                             bool link12, bool dag, bool xpay, int red, hipStream_t s) {
-    if (dag) {
-        return xpay ? launch_red<ST, NCL, true, true>(a, call, prec, link12, red, s)
-                    : launch_red<ST, NCL, true, false>(a, call, prec, link12, red, s);
-    }
-    return xpay ? launch_red<ST, NCL, false, true>(a, call, prec, link12, red, s)
-                : launch_red<ST, NCL, false, false>(a, call, prec, link12, red, s);
-}
-
-template <typename ST>
-static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Phases &ph,
-                                 const HopCall &call, int red, hipStream_t s) {
-    using R = Real<ST>;
-    HopArgs<R> a;
-    a.gauge = call.gauge;
-    for (int q = 0; q < 2; ++q) {
-        a.in[q] = call.in[q];
-        a.xs[q] = call.xs[q];
-        a.out[q] = call.out[q];
-        a.aux[q] = call.aux[q];
-    }
-    a.g = g;
-    a.first_par = call.first_par;
-    a.npar = call.npar;
-    a.nrhs = call.nrhs < 1 ? 1 : call.nrhs;
-    a.nb_rhs = g.bpp * call.npar;
-    a.ngroups = a.nrhs;
-    a.chunk = 1;
-    a.tgroup = 0;
-    {
-        const int A = g.Lxh * g.L[1] * g.L[2];
-        a.ntile_t = A % kBlock == 0 ? A / kBlock : 0;
-    }
-    a.nblocks = a.nb_rhs * a.nrhs;
-    a.fstride = call.fstride;
-    a.c = R(call.c);
-    for (int mu = 0; mu < 4; ++mu) {
-        a.phr[mu] = R(ph.re[mu]);
-        a.phi[mu] = R(ph.im[mu]);
-    }
-    a.skip = call.skip;
-    if (call.red) a.red = *call.red;
-    else a.red = Reduce{nullptr, nullptr, kEpiNone, nullptr};
-    a.gtab = call.gtab;
-    a.ksc = call.ksc;
-    a.cmul = R(call.cmul);
-    a.cpow = call.cpow;
-    const bool xpay = call.xs[call.first_par] != nullptr;
-    return link12 ? launch_ncl<ST, 6>(a, call, prec, link12, call.dag, xpay, red, s)
-                  : launch_ncl<ST, 9>(a, call, prec, link12, call.dag, xpay, red, s);
-}
-
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s) {
     int red = kRedNone;
@@ -772,9 +111,9 @@ hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
     if (call.npar < 1 || call.npar > 2 || !call.out[call.first_par] ||
         !call.in[1 - call.first_par])
         return hipErrorInvalidValue;
-    return with_storage(prec, [&](auto tag) {
-        return launch_storage<decltype(tag)>(g, prec, link12, ph, call, red, s);
-    });
+    if (prec == WL_F64) return launch_storage_f64(g, prec, link12, ph, call, red, s);
+    if (prec == WL_F32) return launch_storage_f32(g, prec, link12, ph, call, red, s);
+    return launch_storage_f16(g, prec, link12, ph, call, red, s);
 }
 
 }  // namespace wl

@@ -114,7 +114,8 @@ template <typename ST, int NCL> constexpr int link_cw() {
 
 // NC complex numbers of site i: NC / CW arrays of S chunks of CW complex, then
 // (if NC % CW != 0) one array of S chunks holding the remaining NC % CW.
-template <typename ST, int NC, int CW>
+// NT: read-once data (a streaming load that L2 need not keep).
+template <typename ST, int NC, int CW, bool NT = false>
 __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Real<ST>> *v) {
     using T = typename Vec<ST, CW>::T;
     using R = Real<ST>;
@@ -122,7 +123,9 @@ __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Re
     const T *p = static_cast<const T *>(base);
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
-        const T c = p[j * S + i];
+        T c;
+        if constexpr (NT) c = __builtin_nontemporal_load(&p[j * S + i]);
+        else c = p[j * S + i];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             v[CW * j + k].re = R(c[2 * k]);
@@ -131,7 +134,10 @@ __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Re
     }
     if constexpr (TL > 0) {
         using TT = typename Vec<ST, TL>::T;
-        const TT c = reinterpret_cast<const TT *>(p + size_t(NF) * S)[i];
+        const TT *q = reinterpret_cast<const TT *>(p + size_t(NF) * S) + i;
+        TT c;
+        if constexpr (NT) c = __builtin_nontemporal_load(q);
+        else c = *q;
 #pragma unroll
         for (int k = 0; k < TL; ++k) {
             v[CW * NF + k].re = R(c[2 * k]);
@@ -178,12 +184,15 @@ __device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<R
 // ---- spinors: one site of one parity block --------------------------------
 // Half blocks hold the 24 binary16 values of psi/s (s = max |component| of the
 // site, so every stored value lies in [-1, 1]) followed by the S scales.
-template <typename ST>
+template <typename ST, bool NT = false>
 __device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<Real<ST>> v[12]) {
-    load_cplx<ST, 12, spinor_cw<ST>()>(blk, S, i, v);
+    load_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v);
     if constexpr (std::is_same<ST, Half>::value) {
-        const float s = reinterpret_cast<const float *>(static_cast<const char *>(blk) +
-                                                        size_t(S) * 48)[i];
+        const float *sp = reinterpret_cast<const float *>(static_cast<const char *>(blk) +
+                                                          size_t(S) * 48) + i;
+        float s;
+        if constexpr (NT) s = __builtin_nontemporal_load(sp);
+        else s = *sp;
 #pragma unroll
         for (int k = 0; k < 12; ++k) v[k] = s * v[k];
     }
@@ -209,10 +218,10 @@ __device__ __forceinline__ const void *link_block(const void *gauge, int S, int 
     return static_cast<const char *>(gauge) + size_t(par * 4 + mu) * NCL * cbytes<ST>() * S;
 }
 
-template <typename ST, int NCL>
+template <typename ST, int NCL, bool NT = false>
 __device__ __forceinline__ void load_link_raw(const void *gauge, int S, int par, int mu, int i,
                                               cpx<Real<ST>> *u) {
-    load_cplx<ST, NCL, link_cw<ST, NCL>()>(link_block<ST, NCL>(gauge, S, par, mu), S, i, u);
+    load_cplx<ST, NCL, link_cw<ST, NCL>(), NT>(link_block<ST, NCL>(gauge, S, par, mu), S, i, u);
 }
 
 template <typename ST, int NCL>
