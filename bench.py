@@ -518,7 +518,7 @@ def main():
     traffic = profiled_traffic(args.link12) if args.workload == "32^3x64" else None
     roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "wl::hop_kernel<float, %d, false, false, 0, 1> (even-odd hop, FP32)"
+                "kernel": "wl::hop_kernel<float, %d, false, false, 0, 1, true> (even-odd hop, FP32)"
                           % (6 if args.link12 else 9),
                 "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
                 "frac_of_copy": ach / best_copy}
