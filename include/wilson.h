@@ -87,6 +87,14 @@ extern "C" {
                                 lattices); the solve waits for `stream` to
                                 drain, then runs on a library-owned stream */
 
+/* ---- environment ----------------------------------------------------------
+ * WL_TUNE=0             no autotuning of launch shapes (see wl_tuning_report)
+ * WL_TUNE_FILE=path     keep the autotuner's choices in this file
+ * WL_TUNE_FORCE=n,c,g   impose one launch shape on every hop launch (testing)
+ * WL_DELTA_F32=d        reliable-update threshold of FP32-inner mixed CG
+ *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.1)
+ * None of these changes a result's bits except the WL_DELTA_* thresholds.  */
+
 /* ---- status codes -------------------------------------------------------- */
 #define WL_OK          0
 #define WL_NOCONV      1     /* maxiter reached                               */
