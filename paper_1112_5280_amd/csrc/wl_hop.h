@@ -468,10 +468,10 @@ static hipError_t launch_kernel(HopArgs<Real<ST>> a, int chunk, int tgroup, hipS
     a.nblocks = a.nb_rhs * a.ngroups;
     a.chunk = std::max(1, std::min(chunk, a.nb_rhs));
     a.tgroup = tgroup;
-    // links of a one-parity launch are read once: streaming loads keep L2 for
-    // the neighbour spinors. Both parities read every link, the second read
-    // wants it cached.
-    if (a.npar == 1 && WL_NT_LINKS)
+    // links of a one-parity launch of one RHS group are read once: streaming
+    // loads keep L2 for the neighbour spinors. When both parities, or several
+    // RHS groups, read every link, the later reads want it cached.
+    if (a.npar == 1 && a.ngroups == 1 && WL_NT_LINKS)
         hipLaunchKernelGGL((hop_kernel<ST, NCL, DAG, XPAY, RED, NR, true>), dim3(a.nblocks),
                            dim3(kBlock), 0, s, a);
     else
