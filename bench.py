@@ -239,6 +239,71 @@ def uneven64(w, torch, synth, np):
     return out
 
 
+def small_configs(w, torch, synth, n_launch):
+    """The two small configurations. 4^4 (Haar, kappa 0.12, FP64): one M apply
+    and a CGNR solve -- latency-bound, reported in microseconds. 16^3 x 32
+    (exp(i 0.3 H), kappa 0.15): every operator variant (its working set fits in
+    the 256 MB Infinity Cache, so these rates are cache-resident, not HBM) and
+    BiCGStab on the even-odd system, plain FP64 and mixed."""
+    s = torch.cuda.current_stream()
+    out = {}
+    dims, kappa = (4, 4, 4, 4), 0.12
+    U = synth.gauge_haar(dims, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    O = w.empty_spinor(dims)
+    t = time_kernel(lambda: w.wilson_dslash(G, B, O, dims, kappa, stream=s), n_launch, torch)
+    c1 = {"lattice": list(dims), "M_apply_us": t * 1e6}
+    X = w.empty_spinor(dims)
+    for f, name in ((0, "cg_full_f64"), (w.EO, "cg_eo_f64"), (w.EO | w.GRAPH, "cg_eo_f64_graph")):
+        w.solve_cg(G, B, X, dims, kappa, flags=f, stream=s)
+        st, dt = timed(lambda: w.solve_cg(G, B, X, dims, kappa, flags=f, stream=s), torch)
+        assert st["status"] == 0 and st["true_res"] <= 1e-10, st
+        c1[name] = {"us": dt * 1e6, "iterations": st["iterations"], "true_res": st["true_res"]}
+    out["4^4"] = c1
+
+    dims, kappa = (16, 16, 16, 32), 0.15
+    V = synth.volume(dims)
+    U = synth.gauge_smooth(dims, 0.30, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    ops = {}
+    for prec, pname in ((w.F64, "f64"), (w.F32, "f32")):
+        for lk, lname in ((w.LINK18, "18"), (w.LINK12, "12")):
+            G = w.pack_gauge(U, dims, prec | lk)
+            P = w.pack_spinor(b, dims, prec)
+            O = w.empty_spinor(dims, prec)
+            Oh = w.empty_spinor(dims, prec, 1)
+            per = 2 * SPINOR_BYTES[prec] + 4 * COMPLEX_BYTES[prec] * (6 if lk else 9)
+            for dag, dname in ((0, "M"), (w.DAG, "Mdag")):
+                f = prec | lk | dag
+                tm = time_kernel(lambda: w.wilson_dslash(G, P, O, dims, kappa, flags=f, stream=s),
+                                 n_launch, torch)
+                ops["%s_%s_%s" % (dname, pname, lname)] = {
+                    "us": tm * 1e6, "GBs": per * V / tm / 1e9, "GFLOPs": 1368 * V / tm / 1e9}
+            f = prec | lk | w.HOP
+            te = time_kernel(lambda: w.wilson_dslash_eo(G, w.parity_block(P, dims, prec, 0), Oh,
+                                                        dims, kappa, 1, flags=f, stream=s),
+                             n_launch, torch)
+            ops["Deo_%s_%s" % (pname, lname)] = {
+                "us": te * 1e6, "GBs": (per + 4 * COMPLEX_BYTES[prec] * (6 if lk else 9)) * V / 2 / te / 1e9,
+                "GFLOPs": 1320 * V / 2 / te / 1e9}
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    solves = {}
+    for f, name in ((w.EO, "bicgstab_eo_f64"), (w.EO | w.MIXED, "bicgstab_eo_mixed_f32"),
+                    (w.EO | w.MIXED | w.F16S, "bicgstab_eo_mixed_f16"), (w.EO, "cg_eo_f64"),
+                    (w.EO | w.MIXED, "cg_eo_mixed_f32")):
+        fn = w.solve_bicgstab if name.startswith("bicgstab") else w.solve_cg
+        st, dt = timed(lambda: fn(G, B, X, dims, kappa, maxiter=20000, flags=f, stream=s), torch)
+        solves[name] = {"ms": dt * 1e3, "status": st["status_name"], "iterations": st["iterations"],
+                        "restarts": st["restarts"], "true_res": st["true_res"]}
+    out["16^3x32"] = {"lattice": list(dims), "kappa": kappa, "cache_resident": True,
+                      "operators": ops, "solves": solves}
+    return out
+
+
 SERVE_SIZES = (((8, 8, 8, 8), 0.40), ((16, 16, 16, 32), 0.35), ((24, 24, 24, 48), 0.20),
                ((32, 32, 32, 64), 0.05))
 
@@ -283,8 +348,10 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
         size, kappa, fld, src, gaps = draw(n + warm, seed)
         arrive = np.zeros(n + warm) if rate is None else np.cumsum(gaps) / rate
         lat, lag, status, iters = [], [], [], []
+        lat_k = {k: [] for k in range(len(SERVE_SIZES))}
         done_t = []
-        srv = w.Server(hbm_budget=int(budget_gb * (1 << 30)), slots=nslots, flags=flags)
+        srv = w.Server(hbm_budget=int(budget_gb * (1 << 30)), slots=nslots, flags=flags,
+                       maxiter=20000)
         held = {}
         stalls = [0]
 
@@ -300,6 +367,7 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
                     xpool[k].put(x)
                     if i >= warm:
                         lat.append(tm["finished"] - tm["submitted"] + late)
+                        lat_k[k].append(lat[-1])
                         status.append(st["status"])
                         iters.append(st["iterations"])
                         done_t.append(tm["finished"])
@@ -353,7 +421,10 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
                 "converged": ok, "mean_iterations": float(np.mean(iters)),
-                "buffer_stalls": stalls[0]}
+                "buffer_stalls": stalls[0],
+                "by_size": {"x".join(map(str, SERVE_SIZES[k][0])): {
+                    "requests": len(v), "p50_ms": float(np.percentile(v, 50)) * 1e3,
+                    "p99_ms": float(np.percentile(v, 99)) * 1e3} for k, v in lat_k.items() if v}}
 
     mixed = w.EO | w.MIXED | w.F16S
     out = {"hbm_budget_gb": budget_gb, "sizes": [[list(d), p] for d, p in SERVE_SIZES],
@@ -523,6 +594,8 @@ def main():
                 "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
                 "frac_of_copy": ach / best_copy}
 
+    small = small_configs(w, torch, synth, args.kernel_launches)
+
     batch = uneven = None
     if not args.no_batch:
         del G64, B, X, work
@@ -587,6 +660,7 @@ def main():
         "device_copy": copy,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "small_configs": small,
         "batch12_point_sources": batch,
         "uneven64_lattices": uneven,
         "serving": serve,

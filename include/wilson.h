@@ -92,7 +92,7 @@ extern "C" {
  * WL_TUNE_FILE=path     keep the autotuner's choices in this file
  * WL_TUNE_FORCE=n,c,g   impose one launch shape on every hop launch (testing)
  * WL_DELTA_F32=d        reliable-update threshold of FP32-inner mixed CG
- *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.1)
+ *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.2)
  * None of these changes a result's bits except the WL_DELTA_* thresholds.  */
 
 /* ---- status codes -------------------------------------------------------- */

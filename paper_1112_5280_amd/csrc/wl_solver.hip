@@ -32,7 +32,8 @@ namespace wl {
 // ---------------------------------------------------------------------------
 // Workspace layout
 // ---------------------------------------------------------------------------
-constexpr int kVec64 = 8;   // FP64 full spinors
+constexpr int kVec64 = 9;   // FP64 full spinors (the last keeps the best iterate)
+constexpr int kVecBatch = 8;   // FP64 full spinors per RHS of a batched solve
 constexpr int kVec32 = 10;  // FP32 full spinors (mixed precision)
 constexpr size_t kAlign = 256;
 
@@ -357,14 +358,19 @@ struct LoVecs {
 // residual reduction between reliable updates, per inner precision
 // (measured on the 32^3 x 64 solve: FP32 inner 0.1 -> 11 updates, 147 ms;
 // 3e-3 -> 5 updates, 137 ms, same 152 iterations. FP16 inner 0.2 -> 15
-// updates, 99 ms; 0.1 -> 11, 93 ms; 0.05 adds iterations; 0.02 needs 255.)
-// WL_DELTA_F32 / WL_DELTA_F16 override them.
+// updates, 99 ms; 0.1 -> 11, 93 ms but smaller lattices then stall below the
+// FP16 noise floor; 0.05 adds iterations; 0.02 needs 255.) WL_DELTA_F32 /
+// WL_DELTA_F16 override them.
 static double reliable_delta(int prec) {
     const char *v = std::getenv(prec == WL_F16S ? "WL_DELTA_F16" : "WL_DELTA_F32");
     const double d = v ? std::atof(v) : 0.0;
     if (d > 0.0 && d < 1.0) return d;
-    return prec == WL_F16S ? 0.1 : 3e-3;
+    return prec == WL_F16S ? 0.2 : 3e-3;
 }
+
+// An inner loop whose residual has not halved within this many iterations has
+// reached the noise floor of its precision: update from FP64 now.
+constexpr int kInnerStall = 300;
 
 static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, void *r64,
                               void *t64, const LoVecs &lo, double target, double delta,
@@ -401,6 +407,8 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
     ChunkRunner runner(k32.s, k32.graph);
     while (its < maxit) {
         Scalars h = read_scalars(k32.sc, k32.s);
+        double best = h.rr;
+        int best_it = h.iter;
         while (!h.done && its + h.iter < maxit) {
             const int n = std::min(chunk, maxit - its - h.iter);
             runner.run(n, [&](int m) {
@@ -413,6 +421,12 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
                 }
             });
             h = read_scalars(k32.sc, k32.s);
+            if (h.rr < 0.5 * best) {
+                best = h.rr;
+                best_it = h.iter;
+            } else if (h.iter - best_it > kInnerStall) {
+                break;   // at the inner precision's noise floor: reliable update now
+            }
         }
         its += h.iter;
         // reliable update: x += x_lo in FP64, fresh FP64 residual
@@ -658,6 +672,11 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                     if (r2 <= tol2) { status = WL_OK; break; }
                     if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
                     if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
+                    // keep the current iterate: if this Krylov pass leaves x
+                    // worse (a stalled BiCGStab), the solve returns this one
+                    full64.blas(kOpCopy, in.x, ws.v64[8], nullptr, nullptr, nullptr, nullptr,
+                                kEpiNone, false);
+                    const double r2_prev = r2;
                     CoreResult cr;
                     const int left = in.maxiter - total_it;
                     if (bicg) {
@@ -684,7 +703,18 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                     if (eo) eo_reconstruct(k, in.b, in.x);
                     r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
                     flops += tr.flops;
-                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
+                    bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
+                    if (!(r2 < r2_prev)) {   // no progress: restore the kept iterate, stop
+                        full64.blas(kOpCopy, ws.v64[8], in.x, nullptr, nullptr, nullptr, nullptr,
+                                    kEpiNone, false);
+                        r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+                        flops += tr.flops;
+                        bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
+                        status = !std::isfinite(r2) ? WL_BREAKDOWN
+                               : (cr.status == WL_BREAKDOWN ? WL_BREAKDOWN : WL_STAGNATED);
+                        if (r2 <= tol2) status = WL_OK;
+                        break;
+                    }
                     if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
                     else ++since_best;
                     if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
@@ -733,14 +763,27 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                     flops += c.flops * cr.iters;
                     bytes += c.bytes * cr.iters;
                     if (eo) eo_reconstruct(k, ws.v32[5], ws.v32[6]);
+                    // keep the current iterate: a correction from an inner solve
+                    // that stalled may make x worse, and x must stay the best
+                    full64.blas(kOpCopy, in.x, ws.v64[8], nullptr, nullptr, nullptr, nullptr,
+                                kEpiNone, false);
                     check(launch_accum_lo(g, 2, lo, ws.v32[6], in.x, in.s));
+                    const double r2_prev = r2;
                     r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
                     flops += tr.flops;
-                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
+                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0 + 2.0 * 2 * g.Vh * 192.0;
                     ++restarts;
+                    if (!(r2 < r2_prev)) {   // rejected: restore x (and r64), stop
+                        full64.blas(kOpCopy, ws.v64[8], in.x, nullptr, nullptr, nullptr, nullptr,
+                                    kEpiNone, false);
+                        r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+                        flops += tr.flops;
+                        bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
+                        status = std::isfinite(r2) ? WL_STAGNATED : WL_BREAKDOWN;
+                        break;
+                    }
                     if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
                     else ++since_best;
-                    if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
                 }
             }
             out.iterations = total_it;
@@ -779,7 +822,7 @@ static size_t batch_header_bytes(const Geom &g, int nrhs) {
 
 size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs) {
     return batch_header_bytes(g, nrhs) +
-           kVec64 * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, WL_F64));
+           kVecBatch * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, WL_F64));
 }
 
 static void read_scalars_n(const Scalars *dev, int n, hipStream_t s, Scalars *out) {
@@ -844,9 +887,9 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     Scalars *sc = reinterpret_cast<Scalars *>(base);
     double *partials = reinterpret_cast<double *>(
         base + align_up(size_t(nrhs) * sizeof(Scalars) + 4096));
-    char *v[kVec64];
+    char *v[kVecBatch];
     char *p = base + batch_header_bytes(g, nrhs);
-    for (int i = 0; i < kVec64; ++i, p += fs * nrhs) v[i] = p;
+    for (int i = 0; i < kVecBatch; ++i, p += fs * nrhs) v[i] = p;
 
     Space full{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, sc, partials, nullptr};
     full.nrhs = nrhs;

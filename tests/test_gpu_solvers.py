@@ -151,3 +151,25 @@ def test_failure_statuses(w, cfg1):
     st = w.solve_cg(G, zero, X, dims, 0.12)
     assert st["status"] == 0
     assert not gu.to_np(w.unpack_spinor(X, dims)).any()
+
+
+@pytest.mark.parametrize("flags", [0x20 | 0x40, 0x20 | 0x40 | 0x2, 0x0],
+                         ids=["eo-mixed-f32", "eo-mixed-f16", "full-f64"])
+def test_bicgstab_past_critical_kappa_keeps_best_iterate(w, flags):
+    """16^3 x 32, kappa = 0.15 (past the crossing of Re lambda(M) = 0 for these
+    fields): BiCGStab may stagnate or break down (a Krylov scalar vanishes),
+    but the returned x is never worse than the start (x = 0, residual 1) and
+    the reported residual is the oracle's."""
+    dims, kappa = (16, 16, 16, 32), 0.15
+    U = synth.gauge_smooth(dims, 0.3, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    G = w.pack_gauge(U, dims)
+    X = w.empty_spinor(dims)
+    st = w.solve_bicgstab(G, w.pack_spinor(b, dims), X, dims, kappa, maxiter=20000, flags=flags)
+    assert st["status"] in (w.OK, w.NOCONV, w.STAGNATED, w.BREAKDOWN), st
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    res = oracle.true_residual(U, b, x, dims, kappa)
+    assert res <= 1.0, (st, res)
+    assert abs(res - st["true_res"]) <= 1e-6 * max(res, 1e-10) + 1e-12, (st, res)
+    if st["status"] == w.OK:
+        assert res <= 1e-10
