@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 12-point-source and 64-lattice batch measurements")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 4^4 and 16^3x32 configurations")
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
@@ -594,7 +596,7 @@ def main():
                 "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
                 "frac_of_copy": ach / best_copy}
 
-    small = small_configs(w, torch, synth, args.kernel_launches)
+    small = None if args.no_small else small_configs(w, torch, synth, args.kernel_launches)
 
     batch = uneven = None
     if not args.no_batch:
