@@ -324,7 +324,8 @@ int wl_server_next(wl_server *srv, uint64_t *ticket, wl_solve_stats *stats,
 int32_t wl_server_pending(wl_server *srv);
 
 /* Finish every queued and running request, then release the slots, streams
- * and arena. Uncollected results are dropped (solutions are still in x). */
+ * and arena. Uncollected results are dropped (solutions are still in x). No
+ * other call on srv may be in progress or follow. */
 int wl_server_destroy(wl_server *srv);
 
 #ifdef __cplusplus

@@ -118,3 +118,23 @@ def test_server_errors_and_drain(w, fields):
     for s, p in zip(srcs, ps):
         x = gu.to_np(w.unpack_spinor(p.x, dims))
         assert oracle.true_residual(U, s, x, dims, 0.14) <= 1e-10
+
+
+def test_failed_request_does_not_stop_the_server(w, fields):
+    """A request whose source holds a NaN ends in BREAKDOWN; the requests
+    around it are served normally."""
+    dims = (8, 8, 8, 8)
+    U, G, _ = fields[dims]
+    good = synth.gaussian_spinor(dims, 80)
+    bad = good.copy()
+    bad[17, 2, 1] = np.nan
+    ps = [w.Problem(dims, 0.13, G, w.pack_spinor(s, dims), w.zeros_spinor(dims))
+          for s in (good, bad, good)]
+    with w.Server(hbm_budget=2 << 30, slots=2, flags=0x20 | 0x40) as srv:
+        ts = [srv.submit(p) for p in ps]
+        res = [srv.wait(t) for t in ts]
+    assert res[0][0] == 0 and res[2][0] == 0
+    assert res[1][0] == w.BREAKDOWN and res[1][1]["status_name"] == "BREAKDOWN"
+    for k in (0, 2):
+        x = gu.to_np(w.unpack_spinor(ps[k].x, dims))
+        assert oracle.true_residual(U, good, x, dims, 0.13) <= 1e-10
