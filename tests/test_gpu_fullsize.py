@@ -66,3 +66,29 @@ def test_point_source_batch_24x48(w):
     for r in range(n):
         x = gu.to_np(w.unpack_spinor(w.batch_field(X, dims, 0, r), dims))
         assert oracle.true_residual(U, srcs[r], x, dims, kappa) <= 1e-10, r
+
+
+def test_mixed_error_against_oracle_solution(w):
+    """12^3 x 24 with the ill-conditioned 32^3 x 64 parameters (exp(i 0.35 H),
+    kappa = 0.155): the oracle's own CGNR solution at 1e-12 is the reference;
+    every GPU solve (FP64, FP32 inner, FP16 inner; tol 1e-10) stays within the
+    bound two residual-1e-10 solutions can differ by. The errors are printed."""
+    dims, kappa = (12, 12, 12, 24), 0.155
+    U = synth.gauge_smooth(dims, 0.35, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    oracle.set_threads(max(1, len(__import__("os").sched_getaffinity(0))))
+    xstar, ost = oracle.cgnr(U, b, dims, kappa, tol=1e-12)
+    assert oracle.true_residual(U, b, xstar, dims, kappa) <= 1e-12
+    G = w.pack_gauge(U, dims)
+    B = w.pack_spinor(b, dims)
+    X = w.empty_spinor(dims)
+    # ||x - x*|| / ||x*|| <= cond(M) (r(x) + r(x*)); cond(M) on these fields is
+    # at most a few hundred (the eo CG needs ~150 iterations), so 1e-7 is loose
+    for flags, name in ((0x20, "f64"), (0x20 | 0x40, "mixed-f32"), (0x20 | 0x40 | 0x2, "mixed-f16")):
+        st = w.solve_cg(G, B, X, dims, kappa, maxiter=20000, flags=flags)
+        assert st["status"] == 0, (name, st)
+        x = gu.to_np(w.unpack_spinor(X, dims))
+        err = np.linalg.norm(x - xstar) / np.linalg.norm(xstar)
+        print("error vs oracle solution, %s: %.2e (true residual %.2e)"
+              % (name, err, st["true_res"]))
+        assert err <= 1e-7, (name, err)
