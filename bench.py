@@ -167,7 +167,9 @@ def batch12(w, torch, synth, n_launch):
             w.pack_spinor(synth.point_source(dims, site, r // 3, r % 3), dims))
     X = w.empty_batch(dims, n)
     solves = {}
-    for f, name in ((w.EO, "batched_f64_eo"), (w.EO | w.GRAPH, "batched_f64_eo_graph")):
+    for f, name in ((w.EO, "batched_f64_eo"), (w.EO | w.GRAPH, "batched_f64_eo_graph"),
+                    (w.EO | w.MIXED, "batched_mixed_f32_eo"),
+                    (w.EO | w.MIXED | w.F16S, "batched_mixed_f16_eo")):
         work = torch.empty(w.workspace_bytes(dims, f, n), dtype=torch.uint8, device="cuda")
         (code, st), dt = timed(lambda: w.solve_cg_batch(G, B, X, n, dims, kappa, flags=f,
                                                         work=work, stream=s), torch)
@@ -177,7 +179,8 @@ def batch12(w, torch, synth, n_launch):
                         "true_res_max": max(x["true_res"] for x in st)}
         del work
     X1 = w.empty_spinor(dims)
-    for f, name in ((w.EO, "sequential_f64_eo"), (w.EO | w.MIXED, "sequential_mixed_f32_eo")):
+    for f, name in ((w.EO, "sequential_f64_eo"), (w.EO | w.MIXED, "sequential_mixed_f32_eo"),
+                    (w.EO | w.MIXED | w.F16S, "sequential_mixed_f16_eo")):
         work = torch.empty(w.workspace_bytes(dims, f), dtype=torch.uint8, device="cuda")
         def run():
             return [w.solve_cg(G, w.batch_field(B, dims, 0, r), X1, dims, kappa, flags=f,
@@ -191,6 +194,8 @@ def batch12(w, torch, synth, n_launch):
     out["solves"] = solves
     out["batched_vs_sequential_f64"] = (solves["sequential_f64_eo"]["seconds"] /
                                         solves["batched_f64_eo"]["seconds"])
+    out["batched_vs_sequential_mixed_f32"] = (solves["sequential_mixed_f32_eo"]["seconds"] /
+                                              solves["batched_mixed_f32_eo"]["seconds"])
     out["autotuned_rhs_per_thread"] = w.tuning_report().strip().splitlines()
     del G, B, X, X1
     torch.cuda.empty_cache()
@@ -212,7 +217,8 @@ def uneven64(w, torch, synth, np):
         probs.append(w.Problem(dims, kappa, G, B, w.zeros_spinor(dims)))
     s = torch.cuda.current_stream()
     out = {"lattices": 64, "sites_total": int(sum(synth.volume(p.dims) for p in probs))}
-    for f, name in ((w.EO, "f64_eo"), (w.EO | w.GRAPH, "f64_eo_graph")):
+    for f, name in ((w.EO, "f64_eo"), (w.EO | w.GRAPH, "f64_eo_graph"),
+                    (w.EO | w.MIXED, "mixed_f32_eo")):
         work = torch.empty(w.problems_workspace_bytes(probs, f), dtype=torch.uint8,
                            device="cuda")
         w.solve_cg_problems(probs, flags=f, work=work, stream=s)      # warm-up

@@ -37,8 +37,9 @@
  *     FP64: 12 chunks of double2 (one complex each, index spin*3 + colour);
  *     FP32: 6 chunks of float4 (two consecutive complex components each);
  *     FP16 (WL_F16S): 3 chunks of 8 binary16 values holding psi/s, where
- *     s = max |real or imaginary component| of the site, followed by the S
- *     FP32 scales s of the block (52 bytes per site).
+ *     s = 2^e is the power of two with m = f 2^e, f in [0.5, 1), m = max |real
+ *     or imaginary component| of the site (s = 1 for a zero site), followed by
+ *     the S FP32 scales s of the block (52 bytes per site).
  *   gauge: [parity][mu][chunk][S]; link U_mu(x) stored at the parity and
  *     checkerboard index of x. 18-real: the 9 complex entries, row-major;
  *     12-real (WL_LINK12): rows 0 and 1 only, row 2 = conj(row0 x row1) is
@@ -208,10 +209,13 @@ int wilson_dslash_batch(const void *gauge, const void *in, void *out, int32_t nr
 
 /* Batched CGNR: solve M x_r = b_r for 1 <= nrhs <= 64 right-hand sides on one
  * gauge field together. b and x each hold nrhs packed FP64 full spinors one
- * after another; flags as for solve_cg (FP64; WL_EO, WL_LINK12, WL_X0) --
- * WL_MIXED is not supported here (WL_EINVAL). Each RHS has its own Krylov
- * scalars, stops at its own tolerance and is restarted on its own FP64 true
- * residual; `stats` (host, may be NULL) receives nrhs entries. `work` needs
+ * after another; flags as for solve_cg (WL_EO, WL_LINK12, WL_X0, WL_GRAPH, and
+ * WL_MIXED with an FP32 or FP16-storage inner solve). Each RHS has its own
+ * Krylov scalars, stops at its own tolerance and is restarted on its own FP64
+ * true residual; with WL_MIXED each RHS runs the reliable-update sequence of
+ * solve_cg, the FP64 replacements of all RHS together, so every solution has
+ * the bits of the same RHS solved alone. `stats` (host, may be NULL) receives
+ * nrhs entries. `work` needs
  * wl_workspace_bytes(dims, flags, nrhs) bytes. Returns WL_OK when every RHS
  * met tol, else a non-OK status of some RHS (see stats). Blocks until done. */
 int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
@@ -236,7 +240,7 @@ size_t wl_problems_workspace_bytes(const wl_problem *p, int32_t n, uint32_t flag
  * for many configurations). Problems of one size are solved together as one
  * batched solve (each with its own gauge field and kappa; up to 64 per group),
  * and the groups run concurrently on library-owned streams. flags as for
- * solve_cg_batch (FP64; WL_EO, WL_LINK12, WL_X0, WL_GRAPH). The call waits for
+ * solve_cg_batch (WL_EO, WL_LINK12, WL_X0, WL_GRAPH, WL_MIXED). The call waits for
  * `stream` to drain, then blocks until every problem is done; stats (host,
  * may be NULL) receives n entries in the order of p. Returns WL_OK when every
  * problem met tol, else a non-OK status of some problem. */

@@ -318,8 +318,14 @@ int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], do
     if (!p || n < 1) return fail(WL_EINVAL, "no problems");
     if (!get_phases(phases, &ph, &why)) return fail(WL_EINVAL, why);
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
-    if ((flags & WL_PREC_MASK) != WL_F64 || (flags & (WL_MIXED | WL_DAG | WL_HOP)))
-        return fail(WL_EINVAL, "batched solves are FP64 (no WL_MIXED, WL_DAG or WL_HOP)");
+    {
+        const uint32_t inner = flags & WL_PREC_MASK;
+        if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
+            return fail(WL_EINVAL, "solver buffers are FP64; a lower precision (WL_F32, WL_F16S) "
+                                   "selects the inner solve of WL_MIXED");
+        if (flags & (WL_DAG | WL_HOP))
+            return fail(WL_EINVAL, "WL_DAG / WL_HOP do not apply to solves");
+    }
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WL_EINVAL, "tol must be positive");
     if (maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
     if (!work) return fail(WL_EINVAL, "NULL workspace");
@@ -354,8 +360,14 @@ int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
     if (nrhs < 1 || nrhs > kMaxBatch)
         return fail(WL_EINVAL, "nrhs must be in 1.." + std::to_string(kMaxBatch));
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
-    if ((flags & WL_PREC_MASK) != WL_F64 || (flags & (WL_MIXED | WL_DAG | WL_HOP)))
-        return fail(WL_EINVAL, "batched solves are FP64 (no WL_MIXED, WL_DAG or WL_HOP)");
+    {
+        const uint32_t inner = flags & WL_PREC_MASK;
+        if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
+            return fail(WL_EINVAL, "solver buffers are FP64; a lower precision (WL_F32, WL_F16S) "
+                                   "selects the inner solve of WL_MIXED");
+        if (flags & (WL_DAG | WL_HOP))
+            return fail(WL_EINVAL, "WL_DAG / WL_HOP do not apply to solves");
+    }
     if (!gauge || !b || !x || !work) return fail(WL_EINVAL, "NULL buffer");
     const size_t fs = 2 * spinor_block_bytes(in.g, WL_F64);
     const char *bb = static_cast<const char *>(b);

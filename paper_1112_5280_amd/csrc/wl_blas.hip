@@ -512,6 +512,15 @@ hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void stop_rhs_kernel(Scalars *sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = 1;
+}
+
+hipError_t launch_stop_rhs(Scalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(stop_rhs_kernel, dim3(1), dim3(64), 0, s, sc);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Streaming copy: the achievable-bandwidth reference. Each thread moves
 // kCopyVec 16-byte vectors, loads first, then non-temporal stores.

@@ -102,7 +102,7 @@ struct HopArgs {
     Reduce red;
     const void *const *gtab;   // per-RHS gauge fields (or null: `gauge` shared)
     const Scalars *ksc;        // per-RHS kappa (or null: `c` shared)
-    R cmul;
+    double cmul;
     int cpow;
 };
 
@@ -311,8 +311,10 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
     for (int r = 0; r < NR; ++r) {
         c[r] = a.c;
         if (a.ksc) {
-            const R k = R(a.ksc[rhs0 + r].kappa);
-            c[r] = a.cpow == 2 ? a.cmul * k * k : (a.cpow == 1 ? a.cmul * k : a.cmul);
+            // in FP64 and in the host's order, then rounded once: the
+            // coefficient of a single solve with this kappa, to the bit
+            const double kd = a.ksc[rhs0 + r].kappa;
+            c[r] = R(a.cpow == 2 ? a.cmul * (kd * kd) : (a.cpow == 1 ? a.cmul * kd : a.cmul));
         }
     }
     int pidx, bo;   // output parity, position of the block in its parity's order
@@ -698,7 +700,7 @@ static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Pha
     else a.red = Reduce{nullptr, nullptr, kEpiNone, nullptr};
     a.gtab = call.gtab;
     a.ksc = call.ksc;
-    a.cmul = R(call.cmul);
+    a.cmul = call.cmul;
     a.cpow = call.cpow;
     const bool xpay = call.xs[call.first_par] != nullptr;
     return link12 ? launch_ncl<ST, 6>(a, call, prec, link12, call.dag, xpay, red, s)

@@ -25,13 +25,16 @@ struct SolveIn {
     // fields (device table) and hopping parameters (host array)
     const void *const *gtab = nullptr;
     const double *kappas = nullptr;
+    const void *const *gauges_host = nullptr;   // the gtab entries, readable on the host
     bool own_stream = false;   // `s` belongs to the library: capture on it directly
 };
 
 int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why);
 
 // batched CG (FP64, full or even-odd): nrhs fields of b and x, st[nrhs]
-size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs);
+// (own_gauges: each RHS has its own gauge field, so a mixed solve keeps one
+// low-precision copy per RHS)
+size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs, bool own_gauges = false);
 int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why);
 
 // independent problems of several lattice sizes, solved concurrently

@@ -182,8 +182,13 @@ __device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<R
 }
 
 // ---- spinors: one site of one parity block --------------------------------
-// Half blocks hold the 24 binary16 values of psi/s (s = max |component| of the
-// site, so every stored value lies in [-1, 1]) followed by the S scales.
+// Half blocks hold the 24 binary16 values of psi/s followed by the S scales.
+// s is the power of two 2^e just above the site's largest |component| m
+// (m = f 2^e, f in [0.5, 1)), so every stored value lies in (-1, 1). Scaling by
+// a power of two is exact and keeps the halves' relative precision; unlike a
+// reciprocal 1/m it cannot overflow when m is an FP32 denormal -- which the
+// far sites of a point-source residual reach after a few iterations, since
+// every hop multiplies by kappa -- and so never turns 0 * inf into NaN.
 template <typename ST, bool NT = false>
 __device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<Real<ST>> v[12]) {
     load_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v);
@@ -204,9 +209,13 @@ __device__ __forceinline__ void store_spinor(void *blk, int S, int i, const cpx<
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
-        const float s = m > 0.f ? m : 1.f;
-        store_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v, 1.f / s);
-        reinterpret_cast<float *>(static_cast<char *>(blk) + size_t(S) * 48)[i] = s;
+        int e = 0;
+        (void)frexpf(m, &e);   // m = 0 gives e = 0, s = 1
+        cpx<float> w[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = {ldexpf(v[k].re, -e), ldexpf(v[k].im, -e)};
+        store_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, w);
+        reinterpret_cast<float *>(static_cast<char *>(blk) + size_t(S) * 48)[i] = ldexpf(1.f, e);
     } else {
         store_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v);
     }
@@ -377,6 +386,8 @@ hipError_t launch_accum_lo(const Geom &g, int npar, int src_prec, const void *x,
 hipError_t launch_set_target(Scalars *sc, double target, hipStream_t s);
 // CG direction update after a residual replacement: beta = sc->rr / rr_old
 hipError_t launch_beta_ratio(Scalars *sc, double rr_old, hipStream_t s);
+// End one RHS's Krylov loop at the current iteration (its kernels then skip)
+hipError_t launch_stop_rhs(Scalars *sc, hipStream_t s);
 // launch_set_target for RHS 0..n-1 of a batch (n <= kMaxBatch), host targets
 hipError_t launch_set_targets(Scalars *sc, const double *targets, int n, hipStream_t s);
 // sc[r].kappa = kappas[r] for r < n (n <= kMaxBatch), host values

@@ -820,9 +820,20 @@ static size_t batch_header_bytes(const Geom &g, int nrhs) {
            align_up(sizeof(double) * kMaxSums * 2 * size_t(g.bpp) * nrhs);
 }
 
-size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs) {
-    return batch_header_bytes(g, nrhs) +
-           kVecBatch * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, WL_F64));
+// low-precision fields per RHS of a mixed batched solve: r, p, t, q, x_lo and
+// the even-odd intermediate
+constexpr int kVecBatchLo = 6;
+
+size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs, bool own_gauges) {
+    size_t n = batch_header_bytes(g, nrhs) +
+               kVecBatch * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, WL_F64));
+    if (flags & WL_MIXED) {
+        const int lo = lo_prec(flags);
+        n += kVecBatchLo * size_t(nrhs) * align_up(2 * spinor_block_bytes(g, lo)) +
+             size_t(own_gauges ? nrhs : 1) * align_up(gauge_bytes(g, lo, flags & WL_LINK12)) +
+             align_up(size_t(nrhs) * sizeof(void *));
+    }
+    return n;
 }
 
 static void read_scalars_n(const Scalars *dev, int n, hipStream_t s, Scalars *out) {
@@ -875,6 +886,162 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
     for (int i = 0; i < k.nrhs; ++i) iters[i] = h[i].iter;
 }
 
+// Mixed-precision CGNR with reliable updates for every RHS of a batch: the
+// per-RHS sequence of cg_reliable (low-precision iterations until the residual
+// has dropped by delta^2, or has not halved in kInnerStall iterations, then an
+// FP64 residual replacement), with all RHS iterating in the same batched
+// launches. An RHS that reaches its stop point idles (its kernels skip) until
+// every RHS has; the replacements then run together. Per RHS the operations
+// are those of the single solve, so each solution keeps its single-solve bits.
+struct BatchLo {
+    void *r, *p, *t, *q, *x;
+    size_t fs;   // field stride of the low-precision batch vectors
+};
+
+static Space one_rhs(const Space &k, int r) {
+    Space o = k;
+    o.nrhs = 1;
+    o.sc = k.sc + r;
+    return o;
+}
+
+static void *field(void *base, size_t fs, int r) { return static_cast<char *>(base) + r * fs; }
+
+static void cg_reliable_batch(Space &k64, Space &k32, const void *rhs, void *x, void *r64,
+                              void *t64, const BatchLo &lo, const double *targets, double delta,
+                              int maxit, int *iters, int *updates, int *status) {
+    const int n = k64.nrhs;
+    const int npar = k64.npar();
+    const Geom &g = *k64.g;
+    const int chunk = chunk_for(g);
+    const size_t fs64 = k64.fstride;
+    std::vector<double> rr(n), rr_new(n), tg(n), best(n);
+    std::vector<int> its(n, 0), stale(n, 0), best_it(n), stopped(n);
+    std::vector<char> active(n, 0);
+    auto residual64 = [&](std::vector<double> &out) {
+        k64.apply(x, t64, false, kEpiNone, nullptr, nullptr);
+        k64.blas(kOpXmy, const_cast<void *>(rhs), t64, nullptr, nullptr, nullptr, nullptr,
+                 kEpiNone, false);
+        k64.apply(t64, r64, true, kEpiNone, nullptr, nullptr);
+        norm2_n(k64, r64, out.data());
+    };
+    auto reload = [&]() {
+        for (int r = 0; r < n; ++r)
+            if (active[r])
+                check(launch_convert_spinor(g, npar, WL_F64, field(r64, fs64, r), k32.prec,
+                                            field(lo.r, lo.fs, r), k64.s));
+        k32.blas(kOpZero, lo.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        for (int r = 0; r < n; ++r)
+            tg[r] = active[r] ? std::max(targets[r], delta * delta * rr[r]) : HUGE_VAL;
+        check(launch_set_targets(k32.sc, tg.data(), n, k32.s));
+    };
+    residual64(rr);
+    for (int r = 0; r < n; ++r) {
+        iters[r] = updates[r] = 0;
+        status[r] = WL_NOCONV;
+        if (!std::isfinite(rr[r])) status[r] = WL_BREAKDOWN;
+        else if (rr[r] <= targets[r]) status[r] = WL_OK;
+        else active[r] = 1;
+    }
+    if (std::find(active.begin(), active.end(), 1) == active.end()) return;
+    reload();
+    k32.blas(kOpCopyNorm2, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+    Scalars h[kMaxBatch];
+    ChunkRunner runner(k32.s, k32.graph);
+    while (true) {
+        read_scalars_n(k32.sc, n, k32.s, h);
+        auto running = [&](int r) { return active[r] && !h[r].done && its[r] + h[r].iter < maxit; };
+        for (int r = 0; r < n; ++r) {
+            best[r] = h[r].rr;
+            best_it[r] = h[r].iter;
+            stopped[r] = 0;
+        }
+        while (true) {
+            int m = 0;
+            for (int r = 0; r < n; ++r)
+                if (running(r)) m = std::max(m, 1);
+            if (!m) break;
+            int steps = chunk;
+            for (int r = 0; r < n; ++r)
+                if (running(r)) steps = std::min(steps, maxit - its[r] - h[r].iter);
+            runner.run(steps, [&](int cnt) {
+                for (int it = 0; it < cnt; ++it) {
+                    const int *skip = &k32.sc->done;
+                    k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
+                    k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
+                    k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
+                    k32.blas(kOpCgP, lo.r, lo.p);
+                }
+            });
+            read_scalars_n(k32.sc, n, k32.s, h);
+            for (int r = 0; r < n; ++r) {
+                if (!active[r] || h[r].done) continue;
+                bool stop = false;
+                if (h[r].rr < 0.5 * best[r]) {
+                    best[r] = h[r].rr;
+                    best_it[r] = h[r].iter;
+                } else if (h[r].iter - best_it[r] > kInnerStall) {
+                    stop = true;   // at the inner precision's noise floor
+                }
+                if (its[r] + h[r].iter >= maxit) stop = true;
+                if (stop) {
+                    stopped[r] = 1;
+                    check(launch_stop_rhs(k32.sc + r, k32.s));
+                }
+            }
+            for (int r = 0; r < n; ++r)
+                if (stopped[r]) h[r].done = 1;   // mirrors the device flag just set
+        }
+        // reliable update of every RHS that iterated in this cycle
+        for (int r = 0; r < n; ++r) {
+            if (!active[r]) continue;
+            its[r] += h[r].iter;
+            check(launch_accum_lo(g, npar, k32.prec, field(lo.x, lo.fs, r), field(x, fs64, r),
+                                  k64.s));
+        }
+        residual64(rr_new);
+        bool any = false;
+        for (int r = 0; r < n; ++r) {
+            if (!active[r]) continue;
+            updates[r] += 1;
+            if (!std::isfinite(rr_new[r])) {
+                status[r] = WL_BREAKDOWN;
+                active[r] = 0;
+            } else if (rr_new[r] <= targets[r]) {
+                status[r] = WL_OK;
+                active[r] = 0;
+            } else {
+                stale[r] = rr_new[r] < 0.5 * rr[r] ? 0 : stale[r] + 1;
+                if (stale[r] > 8) {
+                    status[r] = WL_STAGNATED;
+                    active[r] = 0;
+                } else if (its[r] >= maxit) {
+                    status[r] = WL_NOCONV;
+                    active[r] = 0;
+                } else {
+                    rr[r] = rr_new[r];
+                    any = true;
+                }
+            }
+        }
+        if (!any) break;
+        reload();
+        k32.blas(kOpNorm2, lo.r, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
+        for (int r = 0; r < n; ++r) {
+            if (!active[r]) continue;
+            Space o = one_rhs(k32, r);
+            void *lr = field(lo.r, lo.fs, r), *lp = field(lo.p, lo.fs, r);
+            if (!stopped[r] && h[r].done && h[r].status == WL_OK && h[r].beta > 0.0 && h[r].rr > 0.0) {
+                check(launch_beta_ratio(k32.sc + r, h[r].rr / h[r].beta, k32.s));
+                o.blas(kOpCgP, lr, lp, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+            } else {
+                o.blas(kOpCopy, lr, lp, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+            }
+        }
+    }
+    for (int r = 0; r < n; ++r) iters[r] = its[r];
+}
+
 int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *why) {
     const auto t0 = std::chrono::steady_clock::now();
     SolveIn in = in0;
@@ -901,6 +1068,50 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     full.gtab = k.gtab = in.gtab;
     full.per_kappa = k.per_kappa = in.kappas != nullptr;
 
+    // mixed precision: low-precision batch vectors, gauge copies and table
+    const bool mixed = in.flags & WL_MIXED;
+    const int lo = lo_prec(in.flags);
+    const bool own_gauges = in.gtab != nullptr;
+    BatchLo lov{};
+    Space k32 = k;
+    if (mixed) {
+        lov.fs = align_up(2 * spinor_block_bytes(g, lo));
+        void **lv[5] = {&lov.r, &lov.p, &lov.t, &lov.q, &lov.x};
+        for (int i = 0; i < 5; ++i, p += lov.fs * nrhs) *lv[i] = p;
+        void *tmp32 = p;
+        p += lov.fs * nrhs;
+        const size_t gb = align_up(gauge_bytes(g, lo, link12));
+        char *g32 = p;
+        p += gb * (own_gauges ? nrhs : 1);
+        const void **gtab32 = reinterpret_cast<const void **>(p);
+        k32 = Space{&g, lo, link12, in.ph, g32, in.kappa, eo, in.s, sc, partials, tmp32};
+        k32.nrhs = nrhs;
+        k32.fstride = lov.fs;
+        k32.graph = k.graph;
+        k32.per_kappa = k.per_kappa;
+        try {
+            if (own_gauges) {
+                if (!in.gauges_host) throw Fail{hipErrorInvalidValue};
+                std::vector<const void *> t32(nrhs);
+                for (int r = 0; r < nrhs; ++r) {
+                    t32[r] = g32 + r * gb;
+                    check(launch_convert_gauge(g, link12, in.gauges_host[r], lo,
+                                               const_cast<void *>(t32[r]), in.s));
+                }
+                check(hipMemcpyAsync(gtab32, t32.data(), nrhs * sizeof(void *),
+                                     hipMemcpyHostToDevice, in.s));
+                check(hipStreamSynchronize(in.s));
+                k32.gtab = gtab32;
+            } else {
+                check(launch_convert_gauge(g, link12, in.gauge, lo, g32, in.s));
+            }
+        } catch (const Fail &f) {
+            *why = std::string("HIP error preparing the mixed batch: ") + hipGetErrorString(f.err);
+            return WL_EHIP;
+        }
+    }
+    std::vector<int> updates(nrhs, 0), upd(nrhs, 0), core_status(nrhs, 0);
+
     std::vector<double> b2(nrhs), r2(nrhs), mb2(nrhs), eta(nrhs, in.tol), targets(nrhs);
     std::vector<int> iters(nrhs, 0), total(nrhs, 0), restarts(nrhs, 0), status(nrhs, WL_NOCONV);
     std::vector<int> since_best(nrhs, 0);
@@ -908,7 +1119,8 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     double flops = 0, bytes = 0;
     int ret = WL_OK;
     const Cost tr = apply_cost(g, WL_F64, link12, false);
-    const Cost ic = iter_cost(g, WL_F64, link12, eo, false);
+    const Cost ic = iter_cost(g, (in.flags & WL_MIXED) ? lo_prec(in.flags) : WL_F64, link12, eo,
+                              false);
     auto true_res = [&]() {
         full.apply(in.x, v[6], false, kEpiNone, nullptr, nullptr);
         full.blas(kOpXmy, const_cast<void *>(in.b), v[6], nullptr, nullptr, nullptr, nullptr,
@@ -970,7 +1182,21 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
                 targets[r] = active[r] ? eta[r] * eta[r] * mb2[r] : HUGE_VAL;
                 if (active[r]) left = std::max(left, in.maxiter - total[r]);
             }
-            cg_core_batch(k, rhs, in.x, v[0], v[1], v[2], v[3], targets.data(), left, iters.data());
+            if (mixed) {
+                cg_reliable_batch(k, k32, rhs, in.x, v[0], v[2], lov, targets.data(),
+                                  reliable_delta(lo), left, iters.data(), upd.data(),
+                                  core_status.data());
+                const Cost u = apply_cost(g, WL_F64, link12, eo);
+                const double Vs = eo ? g.Vh : 2.0 * g.Vh;
+                for (int r = 0; r < nrhs; ++r) {
+                    updates[r] += upd[r];
+                    flops += upd[r] * 2 * u.flops;
+                    bytes += upd[r] * (2 * u.bytes + Vs * (6 * 192.0 + 3 * site_bytes(lo)));
+                }
+            } else {
+                cg_core_batch(k, rhs, in.x, v[0], v[1], v[2], v[3], targets.data(), left,
+                              iters.data());
+            }
             for (int r = 0; r < nrhs; ++r) {
                 total[r] += iters[r];
                 flops += ic.flops * iters[r];
@@ -1002,6 +1228,7 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
             st[r].status = status[r];
             st[r].iterations = total[r];
             st[r].restarts = restarts[r];
+            st[r].reliable_updates = updates[r];
             st[r].true_res = b2[r] > 0.0 ? std::sqrt(r2[r] / b2[r]) : 0.0;
             st[r].seconds = secs;
             st[r].flops = flops / nrhs;
@@ -1052,7 +1279,7 @@ static std::vector<Group> plan_groups(const wl_problem *p, int n, uint32_t flags
             gr.off = off;
             const size_t m = gr.idx.size();
             off += align_up(m * sizeof(void *)) + 2 * m * gr.fs +
-                   workspace_bytes_batch(g, flags, int(m));
+                   workspace_bytes_batch(g, flags, int(m), true);
             gs.push_back(gr);
         }
     }
@@ -1124,6 +1351,7 @@ int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int m
             in.work = ws;
             in.s = s;
             in.gtab = gtab;
+            in.gauges_host = ptrs.data();
             in.kappas = kap.data();
             in.own_stream = true;
             gstatus[gi] = run_cg_batch(in, m, gst[gi].data(), &gwhy[gi]);

@@ -107,8 +107,11 @@ def test_problem_argument_checks(w):
         arr, n, ph, tol, 10, flags, _p(32), work, st, None)
     assert call(n=0) == -1
     assert call(work=need - 1) == -2 and "workspace" in w.last_error()
-    assert call(flags=w.MIXED) == -1
-    assert call(flags=w.F32) == -1
+    assert call(flags=w.F32) == -1                # low precision without WL_MIXED
+    assert call(flags=w.DAG) == -1
+    # a mixed solve needs more scratch than the FP64 one it was sized for
+    assert call(flags=w.MIXED) == -2
+    assert w.lib.wl_problems_workspace_bytes(arr, 2, w.MIXED) > need
     assert call(tol=-1.0) == -1
     arr[1].dims = w._dims((4, 4, 3, 8))
     assert call() == -1 and "problem 1" in w.last_error()

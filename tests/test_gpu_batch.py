@@ -112,7 +112,7 @@ def test_batch_argument_errors(w):
     with pytest.raises(w.WilsonError):
         w.solve_cg_batch(G, B, B, 3, dims, 0.1)                        # overlap
     with pytest.raises(w.WilsonError):
-        w.solve_cg_batch(G, B, w.empty_batch(dims, 3), 3, dims, 0.1, flags=w.MIXED)
+        w.solve_cg_batch(G, B, w.empty_batch(dims, 3), 3, dims, 0.1, flags=w.F32)
     with pytest.raises(w.WilsonError):
         w.wilson_dslash_batch(G, B, B, 3, dims, 0.1)
 
@@ -151,3 +151,32 @@ def test_stream_copy(w, nbytes):
     gu.sync()
     assert torch.equal(dst[:nbytes], src)
     assert not dst[nbytes:].any()              # nothing written past the end
+
+
+@pytest.mark.parametrize("flags", [0x20 | 0x40, 0x20 | 0x40 | 0x2, 0x40, 0x20 | 0x40 | 0x4 | 0x100],
+                         ids=["eo-mixed-f32", "eo-mixed-f16", "full-mixed-f32",
+                              "eo-mixed-f32-link12-graph"])
+def test_mixed_batch_equals_solo_mixed_solves(w, flags):
+    """Reliable-update mixed CG over a batch: every RHS follows the single
+    solve's sequence, so each solution and iteration count is the solo one."""
+    dims = (8, 4, 4, 8)
+    kappa = 0.14
+    U = synth.gauge_smooth(dims, 0.3, 0)
+    srcs = point_sources(dims)[:6] + [synth.gaussian_spinor(dims, 7)]
+    n = len(srcs)
+    G = w.pack_gauge(U, dims, flags & 0x4)
+    B = w.empty_batch(dims, n)
+    for r, s in enumerate(srcs):
+        w.batch_field(B, dims, 0, r).copy_(w.pack_spinor(s, dims))
+    X = w.empty_batch(dims, n)
+    code, stats = w.solve_cg_batch(G, B, X, n, dims, kappa, flags=flags)
+    assert code == 0, stats
+    one = w.empty_spinor(dims)
+    for r, s in enumerate(srcs):
+        st = w.solve_cg(G, w.batch_field(B, dims, 0, r), one, dims, kappa, flags=flags)
+        assert st["status"] == 0
+        assert stats[r]["iterations"] == st["iterations"], (r, stats[r], st)
+        assert stats[r]["reliable_updates"] == st["reliable_updates"], (r, stats[r], st)
+        x = gu.to_np(w.unpack_spinor(one, dims))
+        assert np.array_equal(gu.to_np(w.unpack_spinor(w.batch_field(X, dims, 0, r), dims)), x), r
+        assert oracle.true_residual(U, s, x, dims, kappa) <= 1e-10

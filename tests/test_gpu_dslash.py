@@ -100,6 +100,34 @@ def test_pack_roundtrip(w):
     assert (err.reshape(len(psi), -1).max(1) <= smax * 2.0 ** -11 * (1 + 1e-6)).all()
 
 
+def test_f16_storage_far_below_fp32_normal_range(w):
+    """Site magnitudes spread over 10^0 .. 10^-44 (into the FP32 denormals, as
+    the far sites of a point-source residual are after a few CG iterations),
+    plus zero sites: FP16 storage and the FP16 operator stay finite, normal-range
+    sites keep the half-ulp bound, and M agrees with the oracle."""
+    dims = (6, 4, 6, 10)
+    V = synth.volume(dims)
+    rng = np.random.default_rng(11)
+    psi = synth.gaussian_spinor(dims, 12) * 10.0 ** -rng.uniform(0, 44, V)[:, None, None]
+    psi[rng.random(V) < 0.1] = 0
+    got = gu.to_np(w.unpack_spinor(w.pack_spinor(psi, dims, w.F16S), dims, w.F16S))
+    assert np.isfinite(got).all()
+    smax = np.maximum(np.abs(psi.real), np.abs(psi.imag)).reshape(V, -1).max(1)
+    err = np.maximum(np.abs((got - psi).real), np.abs((got - psi).imag)).reshape(V, -1).max(1)
+    normal = smax >= 2.0 ** -100          # values and scales well inside the FP32 range
+    assert (err[normal] <= smax[normal] * 2.0 ** -11 * (1 + 1e-6)).all()
+    # below: denormal products may also be flushed to zero
+    assert (err[~normal] <= smax[~normal] * 2.0 ** -11 * (1 + 1e-6) + 2.0 ** -126).all()
+    assert not got[smax == 0].any()
+    U = synth.gauge_haar(dims, 13)
+    G = w.pack_gauge(U, dims, w.F16S)
+    out = w.empty_spinor(dims, w.F16S)
+    w.wilson_dslash(G, w.pack_spinor(psi, dims, w.F16S), out, dims, 0.15, flags=w.F16S)
+    got = gu.to_np(w.unpack_spinor(out, dims, w.F16S))
+    assert np.isfinite(got).all()
+    gu.assert_close(got, oracle.mop(U, psi, dims, 0.15), gu.TOL[0x2], "M on FP16 storage")
+
+
 def test_free_field_plane_wave_on_gpu(w):
     """Unit links: the GPU operator maps e^{ipx} w to e^{ipx} A(p) w."""
     dims = (4, 6, 2, 8)

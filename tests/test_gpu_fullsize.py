@@ -92,3 +92,32 @@ def test_mixed_error_against_oracle_solution(w):
         print("error vs oracle solution, %s: %.2e (true residual %.2e)"
               % (name, err, st["true_res"]))
         assert err <= 1e-7, (name, err)
+
+
+def test_point_sources_fp16_inner_24x48(w):
+    """The 12 point sources of the 24^3 x 48 propagator with FP16-storage inner
+    iterations, batched and one alone: the residual of a point source falls
+    below the FP32 normal range on its far sites within a few iterations, which
+    the per-site FP16 scale must survive."""
+    dims, kappa = (24, 24, 24, 48), 0.15
+    U = synth.gauge_smooth(dims, 0.30, 0)
+    site = synth.random_site(dims, 2)
+    n = 12
+    G = w.pack_gauge(U, dims)
+    B = w.empty_batch(dims, n)
+    srcs = []
+    for r in range(n):
+        srcs.append(synth.point_source(dims, site, r // 3, r % 3))
+        w.batch_field(B, dims, 0, r).copy_(w.pack_spinor(srcs[-1], dims))
+    X = w.empty_batch(dims, n)
+    flags = 0x20 | 0x40 | 0x2
+    code, stats = w.solve_cg_batch(G, B, X, n, dims, kappa, maxiter=20000, flags=flags)
+    assert code == 0, stats
+    for r in (0, 5, 11):
+        x = gu.to_np(w.unpack_spinor(w.batch_field(X, dims, 0, r), dims))
+        assert oracle.true_residual(U, srcs[r], x, dims, kappa) <= 1e-10, r
+    one = w.empty_spinor(dims)
+    st = w.solve_cg(G, w.batch_field(B, dims, 0, 5), one, dims, kappa, maxiter=20000, flags=flags)
+    assert st["status"] == 0, st
+    assert st["iterations"] == stats[5]["iterations"]
+    assert torch.equal(one, w.batch_field(X, dims, 0, 5))

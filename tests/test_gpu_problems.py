@@ -64,8 +64,8 @@ def check_against_solo(w, specs, probs, stats, flags, tol=1e-10):
         assert np.array_equal(gu.to_np(w.unpack_spinor(one[s["dims"]], s["dims"])), x), i
 
 
-@pytest.mark.parametrize("flags", [0x20, 0x0, 0x20 | 0x4 | 0x100],
-                         ids=["eo", "full", "eo-link12-graph"])
+@pytest.mark.parametrize("flags", [0x20, 0x0, 0x20 | 0x4 | 0x100, 0x20 | 0x40, 0x20 | 0x40 | 0x2],
+                         ids=["eo", "full", "eo-link12-graph", "eo-mixed-f32", "eo-mixed-f16"])
 def test_mixed_sizes_equal_solo_solves(w, flags):
     specs = draw(12, seed=7)
     probs = build(w, specs, flags)
@@ -123,4 +123,4 @@ def test_problem_errors(w):
     with pytest.raises(w.WilsonError):
         w.solve_cg_problems(probs)
     with pytest.raises(w.WilsonError):
-        w.solve_cg_problems(build(w, specs, 0), flags=w.MIXED)
+        w.solve_cg_problems(build(w, specs, 0), flags=w.F32)
