@@ -42,6 +42,8 @@ PINS = {
     "cgnr/bicgstab": "LAPACK dense solve on 4^4; Neumann series for "
                      "kappa < 1/8; free-field plane-wave source",
     "plaquette": "unit links give 1; gauge invariance",
+    "singular_extremes": "LAPACK singular values of the dense operator on "
+                         "2x4x2x4; free-field closed form min/max |lambda(p)|",
 }
 
 
@@ -238,6 +240,46 @@ class Oracle:
         r = _c128(b) - self.mop(U, x, dims, kappa, phases)
         return float(np.linalg.norm(r) / np.linalg.norm(b))
 
+    def singular_extremes(self, U, dims, kappa, steps=300, seed=0,
+                          phases=ANTIPERIODIC_T):
+        """Largest and smallest singular value of M and cond(M) = their ratio.
+
+        Two solutions whose true residuals are rho and rho* differ by at most
+        cond(M) (rho + rho*) relative to the solution, so this condition number
+        is the scale on which solutions from different solvers and precisions
+        are compared. Plain Lanczos tridiagonalisation of A = M^dag M from a
+        complex Gaussian start vector (``seed``); sigma^2 are the extreme
+        eigenvalues of the ``steps`` x ``steps`` tridiagonal matrix. Without
+        reorthogonalisation, lost orthogonality only repeats Ritz values that
+        have converged; it does not move the extreme ones. The smallest Ritz
+        value approaches lambda_min(A) from above, so until it has converged
+        cond is an underestimate. Returns ``(sigma_max, sigma_min, cond)``.
+        """
+        d = _dims(dims)
+        shape = (_vol(d), 4, 3)
+        rng = np.random.default_rng(seed)
+        v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        v /= np.linalg.norm(v)
+        v_prev = np.zeros_like(v)
+        alpha, beta = [], []
+        b_prev = 0.0
+        for _ in range(steps):
+            w = self.mop(U, self.mop(U, v, dims, kappa, phases), dims, kappa,
+                         phases, dagger=True)
+            a = float(np.vdot(v, w).real)
+            w = w - a * v - b_prev * v_prev
+            alpha.append(a)
+            b = float(np.linalg.norm(w))
+            if b <= 1e-13 * abs(a):     # invariant subspace: T is exact
+                break
+            beta.append(b)
+            v_prev, v, b_prev = v, w / b, b
+        k = len(alpha)
+        T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+        ev = np.linalg.eigvalsh(T)
+        smax, smin = float(np.sqrt(ev[-1])), float(np.sqrt(max(ev[0], 0.0)))
+        return smax, smin, smax / smin
+
 
 def default() -> Oracle:
     """The oracle built from ``wilson_oracle.c`` (compiled on first use)."""
@@ -258,7 +300,7 @@ def _forward(name):
 
 for _name in ("set_threads", "max_threads", "gamma", "dslash", "mop",
               "mop_sites", "dslash_sites", "dslash_eo", "schur", "plaquette",
-              "cgnr", "bicgstab", "true_residual"):
+              "cgnr", "bicgstab", "true_residual", "singular_extremes"):
     globals()[_name] = _forward(_name)
 
 

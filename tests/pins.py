@@ -305,9 +305,42 @@ def pin_plaquette(orc, dims=(4, 4, 2, 4)):
     assert abs(p0 - p1) < 1e-13
 
 
+def pin_singular_extremes_dense(orc, dims=(2, 4, 2, 4), seed=25, kappa=0.13):
+    """The Lanczos estimate of M's extreme singular values equals LAPACK's SVD
+    of the dense operator on a Haar field."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, seed)
+    M = _dense_from_apply(
+        lambda e: orc.mop(U, e.reshape(V, 4, 3), dims, kappa, AP).reshape(-1),
+        12 * V)
+    sv = np.linalg.svd(M, compute_uv=False)
+    smax, smin, cond = orc.singular_extremes(U, dims, kappa, steps=12 * V)
+    assert abs(smax - sv[0]) <= 1e-10 * sv[0], (smax, sv[0])
+    assert abs(smin - sv[-1]) <= 1e-8 * sv[-1], (smin, sv[-1])
+    assert abs(cond - sv[0] / sv[-1]) <= 1e-8 * cond
+
+
+def pin_singular_extremes_free_field(orc, dims=(4, 4, 4, 8), kappa=0.12):
+    """Unit links: M is normal (a plane wave of momentum p spans an invariant
+    space on which M acts as A(p)), so its singular values are the moduli
+    |1 - 2k sum cos p +- 2ik sqrt(sum sin^2 p)| over the lattice momenta."""
+    U = synth.gauge_unit(dims)
+    mom = _momenta(dims, AP)
+    mods = []
+    for n in itertools.product(*[range(d) for d in dims]):
+        p = [mom[mu][n[mu]] for mu in range(4)]
+        c = 1 - 2 * kappa * sum(np.cos(p))
+        s = 2 * kappa * np.sqrt(sum(np.sin(x) ** 2 for x in p))
+        mods.append(abs(c + 1j * s))
+    smax, smin, cond = orc.singular_extremes(U, dims, kappa, steps=200)
+    assert abs(smax - max(mods)) <= 1e-10 * max(mods), (smax, max(mods))
+    assert abs(smin - min(mods)) <= 1e-10 * min(mods), (smin, min(mods))
+
+
 ALL_PINS = [
     pin_gamma_algebra, pin_free_field_plane_wave, pin_free_field_spectrum,
     pin_dense_kron, pin_gamma5_hermiticity, pin_gauge_covariance,
     pin_eo_split, pin_schur_dense, pin_sites, pin_solvers_lapack,
     pin_neumann, pin_free_field_solve, pin_plaquette,
+    pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]
