@@ -14,7 +14,8 @@ divided by the step's wall time. ``roofline`` describes the dominant kernel
 (the FP32 even-odd hopping term) timed with HIP events on the stream it runs
 on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice.
 Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
-the same solve with FP16-storage inner iterations, every Dslash variant's GB/s
+the same solve with FP16-storage inner iterations, both mixed solves with
+12-real link storage, every Dslash variant's GB/s
 and GFLOP/s, the 12 point sources of a 24^3 x 48 propagator (batched operator
 and batched solve against single ones), an uneven batch of 64 small lattices
 (one call against 64 solves), and a served Poisson stream of mixed-size
@@ -126,8 +127,9 @@ def timed(fn, torch):
 
 def batch12(w, torch, synth, n_launch):
     """The 12 spin-colour point sources on the 24^3 x 48 lattice (eps = 0.3,
-    kappa = 0.15): batched M GB/s at 432 B per site-RHS (FP64-18), and one
-    batched FP64 eo-CG solve of all 12 against 12 solo solves."""
+    kappa = 0.15): batched M GB/s at 432 B per site-RHS (FP64-18), and the
+    batched eo-CG solves of all 12 (FP64, graph replay, FP32 and FP16 inner)
+    against 12 solo solves."""
     dims, kappa = (24, 24, 24, 48), 0.15
     V = synth.volume(dims)
     U = synth.gauge_smooth(dims, 0.30, 0)
@@ -551,6 +553,29 @@ def main():
                    torch.linalg.vector_norm(x16 - x_dev) / torch.linalg.vector_norm(x_dev))}
         del wk, X16, x16
 
+    # the two mixed solves with 12-real link storage (third row rebuilt in the
+    # kernels): fewer bytes per hop, so a shorter time to solution
+    link12_solves = None
+    if not args.no_fp64_compare and not args.link12:
+        G12 = w.pack_gauge(U, dims, w.F64 | w.LINK12)
+        X12 = w.empty_spinor(dims)
+        link12_solves = {}
+        for f, name, ref in ((w.EO | w.MIXED | w.LINK12, "mixed_f32", ms / 1e3),
+                             (w.EO | w.MIXED | w.F16S | w.LINK12, "mixed_f16",
+                              f16["seconds"] if f16 else None)):
+            wk = torch.empty(w.workspace_bytes(dims, f), dtype=torch.uint8, device="cuda")
+            w.solve_cg(G12, B, X12, dims, kappa, tol=1e-10, maxiter=20000, flags=f, work=wk,
+                       stream=s)
+            st12, dt = timed(lambda: w.solve_cg(G12, B, X12, dims, kappa, tol=1e-10,
+                                                maxiter=20000, flags=f, work=wk, stream=s),
+                             torch)
+            assert st12["status"] == 0 and st12["true_res"] <= 1e-10, st12
+            link12_solves[name] = {"seconds": dt, "iterations": st12["iterations"],
+                                   "true_res": st12["true_res"],
+                                   "speedup_vs_18_real": ref / dt if ref else None}
+            del wk
+        del G12, X12
+
     # Dslash variants, each timed over a run of launches (HIP events)
     variants = {}
     n = args.kernel_launches
@@ -664,6 +689,7 @@ def main():
         "true_res": max(st["true_res"] for st in stats),
         "fp64_solve": fp64,
         "mixed_f16_solve": f16,
+        "link12_solves": link12_solves,
         "dslash_variants": variants,
         "device_copy": copy,
         "roofline": roofline,

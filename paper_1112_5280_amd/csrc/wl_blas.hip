@@ -173,7 +173,22 @@ __global__ void __launch_bounds__(kBlock) finish_kernel(Reduce red, int nb, cons
     double acc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock)
+    // kU loads in flight before they are added, in the same order as one at a
+    // time (the totals keep their bits; only the load latency overlaps)
+    constexpr int kU = 8;
+    int b = threadIdx.x;
+    for (; b + (kU - 1) * kBlock < nb; b += kU * kBlock) {
+        double v[kU][NS];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[u][s] = rr.partials[s * nb + b + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) acc[s] += v[u][s];
+    }
+    for (; b < nb; b += kBlock)
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[s] += rr.partials[s * nb + b];
     constexpr int kWaves = kBlock / 64;
