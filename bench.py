@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serving-merge", type=int, default=8,
+                    help="most waiting requests of one size served as one batch")
     return ap.parse_args()
 
 
@@ -318,7 +320,7 @@ SERVE_SIZES = (((8, 8, 8, 8), 0.40), ((16, 16, 16, 32), 0.35), ((24, 24, 24, 48)
                ((32, 32, 32, 64), 0.05))
 
 
-def serving(w, torch, synth, np, n_req, budget_gb, slots):
+def serving(w, torch, synth, np, n_req, budget_gb, slots, merge):
     """Poisson stream of solve requests against 8 resident gauge fields (two
     exp(i 0.3 H) fields per lattice size, seeds 0..7): sizes 8^4 40 %, 16^3x32
     35 %, 24^3x48 20 %, 32^3x64 5 %; kappa uniform in [0.12, 0.155]; Gaussian
@@ -326,8 +328,9 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
     from seed 4. First the closed-loop saturation rate S (every request queued
     at once), then open-loop streams at 0.5 S and 0.8 S through the server
     (mixed precision, FP16-storage inner solve, `slots` concurrent solves,
-    HBM budget for workspaces), then the 0.5 S stream through a one-slot
-    plain-FP64 server. Latency = arrival to solution ready."""
+    up to `merge` waiting requests of one size solved as one batch, HBM budget
+    for workspaces), then the 0.5 S stream through a one-slot plain-FP64
+    server without merging. Latency = arrival to solution ready."""
     import queue
     import threading
     t = time.time()
@@ -353,7 +356,7 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
         gaps = rng.exponential(1.0, size=n)   # unit-rate inter-arrival gaps
         return size, kappa, fld, src, gaps
 
-    def run(flags, nslots, rate, n, seed, warm):
+    def run(flags, nslots, rate, n, seed, warm, nmerge):
         """One stream; rate None = closed loop (all queued at t = 0)."""
         size, kappa, fld, src, gaps = draw(n + warm, seed)
         arrive = np.zeros(n + warm) if rate is None else np.cumsum(gaps) / rate
@@ -361,7 +364,7 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
         lat_k = {k: [] for k in range(len(SERVE_SIZES))}
         done_t = []
         srv = w.Server(hbm_budget=int(budget_gb * (1 << 30)), slots=nslots, flags=flags,
-                       maxiter=20000)
+                       maxiter=20000, merge=nmerge)
         held = {}
         stalls = [0]
 
@@ -426,7 +429,7 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
         srv.close()
         lat = np.array(lat) * 1e3
         ok = int(sum(1 for s in status if s == 0))
-        return {"requests": n, "warmup_requests": warm, "slots": nslots,
+        return {"requests": n, "warmup_requests": warm, "slots": nslots, "merge": nmerge,
                 "offered_rate": rate, "solves_per_s": n / span,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
@@ -440,17 +443,17 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots):
     out = {"hbm_budget_gb": budget_gb, "sizes": [[list(d), p] for d, p in SERVE_SIZES],
            "kappa": [0.12, 0.155], "resident_fields": 8, "solver": "eo CG, FP16-storage inner, "
            "FP64 reliable updates, tol 1e-10"}
-    sat = run(mixed, slots, None, max(100, n_req // 4), 40, 10)
+    sat = run(mixed, slots, None, max(100, n_req // 4), 40, 10, merge)
     S = sat["solves_per_s"]
     log("serving: closed-loop saturation %.1f solves/s" % S)
     out["closed_loop"] = sat
     out["saturation_solves_per_s"] = S
     for frac, seed in ((0.5, 4), (0.8, 41)):
-        r = run(mixed, slots, frac * S, n_req, seed, 20)
+        r = run(mixed, slots, frac * S, n_req, seed, 20, merge)
         out["open_loop_%.1fS" % frac] = r
         log("serving: %.1f S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
             % (frac, r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
-    r = run(w.EO, 1, 0.5 * S, n_req, 4, 20)
+    r = run(w.EO, 1, 0.5 * S, n_req, 4, 20, 1)
     out["fp64_one_at_a_time_0.5S"] = r
     log("serving: FP64 one at a time at 0.5 S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
         % (r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
@@ -643,7 +646,7 @@ def main():
         torch.cuda.empty_cache()
         t = time.time()
         serve = serving(w, torch, synth, np, args.serving_requests, args.serving_budget_gb,
-                        args.serving_slots)
+                        args.serving_slots, args.serving_merge)
         log("serving measurements in %.1f s" % (time.time() - t))
 
     cpu = None

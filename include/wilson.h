@@ -279,8 +279,14 @@ size_t wl_tuning_report(char *buf, size_t len);
  * is collected. Requests are admitted first-in first-out: the oldest waiting
  * request starts as soon as a slot is idle and its workspace fits in the free
  * arena; each slot is a host thread with its own stream, so the solves of all
- * admitted requests overlap on the device. A request's result does not depend
- * on what else is running (every reduction has a fixed order).
+ * admitted requests overlap on the device. With `merge` > 1 the slot also
+ * takes up to merge - 1 further waiting requests of the same lattice size, if
+ * that lattice has at most 131072 sites (a larger solve fills the device by
+ * itself), oldest first, passing over other sizes, while the batch's workspace fits,
+ * and solves them as one batched CG (each with its own gauge field, kappa,
+ * source and solution; they are admitted and finish together). A request's
+ * result does not depend on what else is running or on its batch mates
+ * (every reduction has a fixed order): it is bitwise its solo solve.
  * ------------------------------------------------------------------------- */
 typedef struct wl_server wl_server;   /* opaque */
 
@@ -292,6 +298,8 @@ typedef struct {
     double tol;           /* relative true-residual target                       */
     int32_t maxiter;      /* iteration limit per request                         */
     double phases[8];     /* boundary phases, as for wilson_dslash               */
+    int32_t merge;        /* most requests of one size solved as one batch,    */
+                          /* 0..64 (0 or 1: every request alone)                */
 } wl_server_config;
 
 /* Timestamps of one request, seconds since the server was created. */

@@ -480,6 +480,7 @@ int wl_server_create(const wl_server_config *cfg, wl_server **out) {
     *out = nullptr;
     if (cfg->hbm_budget == 0) return fail(WL_EINVAL, "hbm_budget must be positive");
     if (cfg->slots < 1 || cfg->slots > 64) return fail(WL_EINVAL, "slots must be in 1..64");
+    if (cfg->merge < 0 || cfg->merge > kMaxBatch) return fail(WL_EINVAL, "merge must be in 0..64");
     if (!get_phases(cfg->phases, &ph, &why)) return fail(WL_EINVAL, why);
     const uint32_t flags = cfg->flags;
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");

@@ -37,6 +37,13 @@ int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *wh
 size_t workspace_bytes_batch(const Geom &g, uint32_t flags, int nrhs, bool own_gauges = false);
 int run_cg_batch(const SolveIn &in, int nrhs, wl_solve_stats *st, std::string *why);
 
+// m problems of one lattice size (own gauge field and kappa each) as one
+// batched CG on stream s, in problem_group_bytes(g, flags, m) bytes of work
+size_t problem_group_bytes(const Geom &g, uint32_t flags, int m);
+int run_problem_group(const wl_problem *const *p, int m, const Geom &g, const Phases &ph,
+                      double tol, int maxiter, uint32_t flags, void *work, hipStream_t s,
+                      wl_solve_stats *st, std::string *why);
+
 // independent problems of several lattice sizes, solved concurrently
 size_t problems_workspace_bytes(const wl_problem *p, int n, uint32_t flags);
 int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int maxiter,

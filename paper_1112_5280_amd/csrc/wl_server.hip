@@ -10,6 +10,7 @@
 // carved by a first-fit allocator with coalescing, so admission by memory is
 // exact and nothing is allocated per request.
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -24,6 +25,9 @@ namespace wl {
 namespace {
 
 constexpr size_t kArenaAlign = 256;
+// Only lattices up to this volume are merged: a larger solve keeps the device
+// busy by itself, and batching it only makes its batch mates finish together.
+constexpr long kMergeMaxSites = 1L << 17;
 
 // First-fit allocator over [0, size) with free-block coalescing.
 class Arena {
@@ -76,7 +80,7 @@ struct Request {
     uint64_t ticket = 0;
     wl_problem p{};
     Geom g{};
-    size_t ws_bytes = 0, ws_off = 0;
+    size_t ws_bytes = 0;
     wl_request_times t{};
     wl_solve_stats st{};
     int status = WL_NOCONV;
@@ -113,27 +117,63 @@ struct wl_server {
 
     bool head_fits() const { return !queue.empty() && arena.can_alloc(queue.front()->ws_bytes); }
 
+    // bytes of a merged batch of m requests of geometry g (one request: the
+    // solo solver's workspace), rounded to the arena's alignment
+    size_t batch_bytes(const Geom &g, int m) const {
+        const size_t n = m == 1 ? workspace_bytes(g, cfg.flags) : problem_group_bytes(g, cfg.flags, m);
+        return (n + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    }
+
+    // the head request and, with merging, the waiting requests of its lattice
+    // size (oldest first) that fit beside it; removes them from the queue
+    // and carves their workspace (lock held, head_fits() true)
+    std::vector<Request *> take_batch(size_t *off, size_t *bytes) {
+        std::vector<Request *> grp{queue.front()};
+        size_t need = queue.front()->ws_bytes;
+        if (cfg.merge > 1 && 2L * grp[0]->g.Vh <= kMergeMaxSites) {
+            const Geom &g = grp[0]->g;
+            for (size_t j = 1; j < queue.size() && int(grp.size()) < cfg.merge; ++j) {
+                Request *q = queue[j];
+                if (std::memcmp(q->p.dims, grp[0]->p.dims, sizeof(q->p.dims)) != 0) continue;
+                const size_t more = batch_bytes(g, int(grp.size()) + 1);
+                if (!arena.can_alloc(more)) break;
+                grp.push_back(q);
+                need = more;
+            }
+        }
+        if (!arena.alloc(need, off)) return {};
+        for (Request *r : grp)
+            for (auto it = queue.begin(); it != queue.end(); ++it)
+                if (*it == r) {
+                    queue.erase(it);
+                    break;
+                }
+        *bytes = need;
+        return grp;
+    }
+
     void slot_loop(int k) {
         const hipError_t e = hipSetDevice(dev);
         std::unique_lock<std::mutex> lk(m);
         for (;;) {
             cv_admit.wait(lk, [&] { return head_fits() || (stopping && queue.empty()); });
             if (queue.empty()) break;   // stopping and drained
-            Request *r = queue.front();
-            size_t off = 0;
-            if (!arena.alloc(r->ws_bytes, &off)) continue;
-            queue.pop_front();
-            r->ws_off = off;
-            r->t.admitted = seconds_since(t0);
+            size_t off = 0, bytes = 0;
+            std::vector<Request *> grp = take_batch(&off, &bytes);
+            if (grp.empty()) continue;
+            const double now = seconds_since(t0);
+            for (Request *r : grp) r->t.admitted = now;
             if (head_fits()) cv_admit.notify_one();   // the next one may start too
             lk.unlock();
 
             std::string why;
+            const int n = int(grp.size());
+            std::vector<wl_solve_stats> st(n);
+            std::vector<int> status(n, WL_EHIP);
             if (e != hipSuccess) {
-                r->status = WL_EHIP;
-                r->st = wl_solve_stats{};
-                r->st.status = WL_EHIP;
-            } else {
+                for (int i = 0; i < n; ++i) st[i].status = WL_EHIP;
+            } else if (n == 1) {
+                Request *r = grp[0];
                 SolveIn in{};
                 in.gauge = r->p.gauge;
                 in.b = r->p.b;
@@ -147,14 +187,27 @@ struct wl_server {
                 in.work = static_cast<char *>(arena_mem) + off;
                 in.s = streams[k];
                 in.own_stream = true;
-                r->status = run_solver(false, in, &r->st, &why);
+                status[0] = run_solver(false, in, &st[0], &why);
+            } else {
+                std::vector<const wl_problem *> ps(n);
+                for (int i = 0; i < n; ++i) ps[i] = &grp[i]->p;
+                run_problem_group(ps.data(), n, grp[0]->g, ph, cfg.tol, cfg.maxiter, cfg.flags,
+                                  static_cast<char *>(arena_mem) + off, streams[k], st.data(),
+                                  &why);
+                for (int i = 0; i < n; ++i) status[i] = st[i].status;
             }
 
             lk.lock();
-            arena.release(r->ws_off, r->ws_bytes);
-            r->t.finished = seconds_since(t0);
-            r->done = true;
-            finished.push_back(r);
+            arena.release(off, bytes);
+            const double fin = seconds_since(t0);
+            for (int i = 0; i < n; ++i) {
+                Request *r = grp[i];
+                r->st = st[i];
+                r->status = status[i];
+                r->t.finished = fin;
+                r->done = true;
+                finished.push_back(r);
+            }
             cv_done.notify_all();
             cv_admit.notify_all();
         }

@@ -1253,8 +1253,75 @@ constexpr size_t kMaxGroupThreads = 8;
 struct Group {
     Geom g;
     std::vector<int> idx;
-    size_t off, fs;
+    size_t off;
 };
+
+size_t problem_group_bytes(const Geom &g, uint32_t flags, int m) {
+    const size_t fs = align_up(2 * spinor_block_bytes(g, WL_F64));
+    return align_up(size_t(m) * sizeof(void *)) + 2 * size_t(m) * fs +
+           workspace_bytes_batch(g, flags, m, true);
+}
+
+// m problems of one lattice size solved as one batch on stream s: sources are
+// gathered into a batch in `work` (problem_group_bytes(g, flags, m) bytes),
+// the batched CG runs with each problem's gauge field and kappa, and the
+// solutions are scattered back. Every problem's result is bitwise its solo one.
+int run_problem_group(const wl_problem *const *p, int m, const Geom &g, const Phases &ph,
+                      double tol, int maxiter, uint32_t flags, void *work, hipStream_t s,
+                      wl_solve_stats *st, std::string *why) {
+    const size_t fs = align_up(2 * spinor_block_bytes(g, WL_F64));
+    const size_t fbytes = 2 * spinor_block_bytes(g, WL_F64);
+    try {
+        char *base = static_cast<char *>(work);
+        const void **gtab = reinterpret_cast<const void **>(base);
+        char *bb = base + align_up(size_t(m) * sizeof(void *));
+        char *xb = bb + m * fs;
+        void *ws = xb + m * fs;
+        std::vector<const void *> ptrs(m);
+        std::vector<double> kap(m);
+        for (int r = 0; r < m; ++r) {
+            ptrs[r] = p[r]->gauge;
+            kap[r] = p[r]->kappa;
+            check(hipMemcpyAsync(bb + r * fs, p[r]->b, fbytes, hipMemcpyDeviceToDevice, s));
+            if (flags & WL_X0)
+                check(hipMemcpyAsync(xb + r * fs, p[r]->x, fbytes, hipMemcpyDeviceToDevice, s));
+        }
+        check(hipMemcpyAsync(gtab, ptrs.data(), m * sizeof(void *), hipMemcpyHostToDevice, s));
+        check(hipStreamSynchronize(s));
+        SolveIn in{};
+        in.gauge = ptrs[0];
+        in.b = bb;
+        in.x = xb;
+        in.g = g;
+        in.kappa = kap[0];
+        in.ph = ph;
+        in.tol = tol;
+        in.maxiter = maxiter;
+        in.flags = flags;
+        in.work = ws;
+        in.s = s;
+        in.gtab = gtab;
+        in.gauges_host = ptrs.data();
+        in.kappas = kap.data();
+        in.own_stream = true;
+        const int status = run_cg_batch(in, m, st, why);
+        for (int r = 0; r < m; ++r)
+            check(hipMemcpyAsync(p[r]->x, xb + r * fs, fbytes, hipMemcpyDeviceToDevice, s));
+        check(hipStreamSynchronize(s));
+        return status;
+    } catch (const Fail &f) {
+        (void)hipStreamSynchronize(s);
+        *why = std::string("HIP error in problem batch: ") + hipGetErrorString(f.err);
+    } catch (const std::exception &e) {
+        (void)hipStreamSynchronize(s);
+        *why = std::string("host error in problem batch: ") + e.what();
+    }
+    for (int r = 0; r < m; ++r) {
+        st[r] = wl_solve_stats{};
+        st[r].status = WL_EHIP;
+    }
+    return WL_EHIP;
+}
 
 static std::vector<Group> plan_groups(const wl_problem *p, int n, uint32_t flags, size_t *total,
                                       std::string *why) {
@@ -1275,11 +1342,8 @@ static std::vector<Group> plan_groups(const wl_problem *p, int n, uint32_t flags
             Group gr;
             gr.g = g;
             gr.idx.assign(same.begin() + a, same.begin() + std::min(same.size(), a + kMaxBatch));
-            gr.fs = align_up(2 * spinor_block_bytes(g, WL_F64));
             gr.off = off;
-            const size_t m = gr.idx.size();
-            off += align_up(m * sizeof(void *)) + 2 * m * gr.fs +
-                   workspace_bytes_batch(g, flags, int(m), true);
+            off += problem_group_bytes(g, flags, int(gr.idx.size()));
             gs.push_back(gr);
         }
     }
@@ -1316,59 +1380,19 @@ int run_problems(const wl_problem *p, int n, const Phases &ph, double tol, int m
         const Group &gr = gs[gi];
         const int m = int(gr.idx.size());
         gst[gi].assign(m, wl_solve_stats{});
+        std::vector<const wl_problem *> ps(m);
+        for (int r = 0; r < m; ++r) ps[r] = &p[gr.idx[r]];
         hipStream_t s = nullptr;
-        try {
-            check(hipSetDevice(dev));   // the device is per host thread
-            check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-            char *base = static_cast<char *>(work) + gr.off;
-            const void **gtab = reinterpret_cast<const void **>(base);
-            char *bb = base + align_up(m * sizeof(void *));
-            char *xb = bb + m * gr.fs;
-            void *ws = xb + m * gr.fs;
-            std::vector<const void *> ptrs(m);
-            std::vector<double> kap(m);
-            const size_t fbytes = 2 * spinor_block_bytes(gr.g, WL_F64);
-            for (int r = 0; r < m; ++r) {
-                const wl_problem &q = p[gr.idx[r]];
-                ptrs[r] = q.gauge;
-                kap[r] = q.kappa;
-                check(hipMemcpyAsync(bb + r * gr.fs, q.b, fbytes, hipMemcpyDeviceToDevice, s));
-                if (flags & WL_X0)
-                    check(hipMemcpyAsync(xb + r * gr.fs, q.x, fbytes, hipMemcpyDeviceToDevice, s));
-            }
-            check(hipMemcpyAsync(gtab, ptrs.data(), m * sizeof(void *), hipMemcpyHostToDevice, s));
-            check(hipStreamSynchronize(s));
-            SolveIn in{};
-            in.gauge = ptrs[0];
-            in.b = bb;
-            in.x = xb;
-            in.g = gr.g;
-            in.kappa = kap[0];
-            in.ph = ph;
-            in.tol = tol;
-            in.maxiter = maxiter;
-            in.flags = flags;
-            in.work = ws;
-            in.s = s;
-            in.gtab = gtab;
-            in.gauges_host = ptrs.data();
-            in.kappas = kap.data();
-            in.own_stream = true;
-            gstatus[gi] = run_cg_batch(in, m, gst[gi].data(), &gwhy[gi]);
-            for (int r = 0; r < m; ++r)
-                check(hipMemcpyAsync(p[gr.idx[r]].x, xb + r * gr.fs, fbytes,
-                                     hipMemcpyDeviceToDevice, s));
-            check(hipStreamSynchronize(s));
-        } catch (const Fail &f) {
-            if (s) (void)hipStreamSynchronize(s);
+        if (hipSetDevice(dev) != hipSuccess ||   // the device is per host thread
+            hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
             gstatus[gi] = WL_EHIP;
-            gwhy[gi] = std::string("HIP error in problem batch: ") + hipGetErrorString(f.err);
-        } catch (const std::exception &e) {
-            if (s) (void)hipStreamSynchronize(s);
-            gstatus[gi] = WL_EHIP;
-            gwhy[gi] = std::string("host error in problem batch: ") + e.what();
+            gwhy[gi] = "HIP error creating the problem batch's stream";
+            return;
         }
-        if (s) (void)hipStreamDestroy(s);
+        gstatus[gi] = run_problem_group(ps.data(), m, gr.g, ph, tol, maxiter, flags,
+                                        static_cast<char *>(work) + gr.off, s, gst[gi].data(),
+                                        &gwhy[gi]);
+        (void)hipStreamDestroy(s);
     };
     // a small pool of host threads takes the groups in order
     std::atomic<size_t> next{0};

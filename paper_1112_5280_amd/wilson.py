@@ -70,7 +70,8 @@ class ServerConfig(ctypes.Structure):
     """The C struct wl_server_config."""
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("tol", ctypes.c_double),
-                ("maxiter", ctypes.c_int32), ("phases", ctypes.c_double * 8)]
+                ("maxiter", ctypes.c_int32), ("phases", ctypes.c_double * 8),
+                ("merge", ctypes.c_int32)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -410,14 +411,17 @@ def tuning_report():
 class Server:
     """A solve server (wl_server_*): requests of any lattice size are admitted
     first-in first-out as solve slots and HBM-budget memory free up, and the
-    admitted solves run concurrently, one stream per slot.
+    admitted solves run concurrently, one stream per slot. With merge > 1 a
+    slot also takes up to merge - 1 more waiting requests of the same lattice
+    size and solves them as one batch (results bitwise those of solo solves).
 
     The caller keeps each request's gauge, b and x tensors alive until the
     request is collected with wait() or next()."""
 
     def __init__(self, hbm_budget, slots=4, flags=EO | MIXED, tol=1e-10, maxiter=100000,
-                 phases=ANTIPERIODIC_T):
+                 phases=ANTIPERIODIC_T, merge=1):
         cfg = ServerConfig()
+        cfg.merge = int(merge)
         cfg.hbm_budget = int(hbm_budget)
         cfg.slots = int(slots)
         cfg.flags = int(flags)

@@ -131,11 +131,13 @@ def test_server_config_checks(w):
         c.tol = k.get("tol", 1e-10)
         c.maxiter = k.get("maxiter", 1000)
         c.phases = w._phases(k.get("phases", w.ANTIPERIODIC_T))
+        c.merge = k.get("merge", 1)
         return c
     h = ctypes.c_void_p()
     create = lambda **k: w.lib.wl_server_create(ctypes.byref(cfg(**k)), ctypes.byref(h))
     assert create(budget=0) == -1 and "budget" in w.last_error()
     assert create(slots=0) == -1 and create(slots=65) == -1
+    assert create(merge=-1) == -1 and create(merge=65) == -1 and "merge" in w.last_error()
     assert create(flags=w.F32) == -1                 # low precision without WL_MIXED
     assert create(flags=w.DAG) == -1
     assert create(tol=0.0) == -1

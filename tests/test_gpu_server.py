@@ -48,12 +48,14 @@ def requests(w, fields, n, seed, link12=False):
     return out
 
 
-@pytest.mark.parametrize("flags", [0x20 | 0x40, 0x20 | 0x40 | 0x2, 0x20 | 0x40 | 0x100 | 0x4,
-                                   0x20],
-                         ids=["mixed-f32", "mixed-f16", "mixed-f32-graph-link12", "f64"])
-def test_served_results_equal_solo_solves(w, fields, flags):
+@pytest.mark.parametrize("flags,merge", [(0x20 | 0x40, 1), (0x20 | 0x40 | 0x2, 1),
+                                         (0x20 | 0x40 | 0x100 | 0x4, 1), (0x20, 1),
+                                         (0x20 | 0x40, 8), (0x20 | 0x40 | 0x2, 8), (0x20, 8)],
+                         ids=["mixed-f32", "mixed-f16", "mixed-f32-graph-link12", "f64",
+                              "mixed-f32-merge8", "mixed-f16-merge8", "f64-merge8"])
+def test_served_results_equal_solo_solves(w, fields, flags, merge):
     reqs = requests(w, fields, 24, seed=5, link12=bool(flags & 0x4))
-    with w.Server(hbm_budget=8 << 30, slots=4, flags=flags) as srv:
+    with w.Server(hbm_budget=8 << 30, slots=4, flags=flags, merge=merge) as srv:
         tickets = {srv.submit(p): i for i, (_, _, p) in enumerate(reqs)}
         got = {}
         while srv.pending():
@@ -138,3 +140,38 @@ def test_failed_request_does_not_stop_the_server(w, fields):
     for k in (0, 2):
         x = gu.to_np(w.unpack_spinor(ps[k].x, dims))
         assert oracle.true_residual(U, good, x, dims, 0.13) <= 1e-10
+
+
+def test_merged_batches(w, fields):
+    """One slot, 9 requests submitted at once: the first is admitted alone,
+    then waiting requests of one size are solved together (same admission and
+    finish time, at most `merge` per batch, sizes never mixed), and every
+    result meets the bound. With a budget for one workspace nothing merges."""
+    flags = 0x20 | 0x40
+    big = (8, 8, 8, 8)
+    one = w.workspace_bytes(big, flags) + 4096
+    for budget, merge, sizes in ((8 << 30, 4, (big, (4, 4, 4, 8))), (one, 4, (big,))):
+        reqs = []
+        for i in range(9):
+            dims = sizes[(i % 3 == 2) % len(sizes)]
+            U, G, _ = fields[dims]
+            b = synth.gaussian_spinor(dims, 300 + i)
+            reqs.append((U, b, w.Problem(dims, 0.13, G, w.pack_spinor(b, dims),
+                                         w.zeros_spinor(dims))))
+        with w.Server(hbm_budget=budget, slots=1, flags=flags, merge=merge) as srv:
+            ts = [srv.submit(p) for _, _, p in reqs]
+            res = [srv.wait(t) for t in ts]
+        groups = {}
+        for (_, _, p), (code, st, tm) in zip(reqs, res):
+            assert code == 0
+            groups.setdefault((tm["admitted"], tm["finished"]), set()).add(p.dims)
+        counts = [sum(1 for (_, _, p), r in zip(reqs, res)
+                      if (r[2]["admitted"], r[2]["finished"]) == k) for k in groups]
+        assert all(len(d) == 1 for d in groups.values())      # one size per batch
+        if len(sizes) == 2:
+            assert 1 < max(counts) <= merge, counts
+        else:
+            assert max(counts) == 1, counts
+        for U, b, p in reqs:
+            x = gu.to_np(w.unpack_spinor(p.x, p.dims))
+            assert oracle.true_residual(U, b, x, p.dims, 0.13) <= 1e-10
