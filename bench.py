@@ -12,7 +12,9 @@ Printed: one JSON line. ``value`` is the whole-step throughput in algorithmic
 (compulsory) GB/s -- the library's per-kernel byte model summed over the step,
 divided by the step's wall time. ``roofline`` describes the dominant kernel
 (the FP32 even-odd hopping term) timed with HIP events on the stream it runs
-on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice.
+on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice
+(all host threads, and one), and on the small configurations (with the 4^4
+CGNR solve).
 Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
 the same solve with FP16-storage inner iterations, both mixed solves with
 12-real link storage, every Dslash variant's GB/s
@@ -666,6 +668,36 @@ def main():
                          "%.2f GFLOP/s at 1368 flop/site; GB/s counts 960 B/site like the "
                          "GPU M" % (nrep, args.workload, dt, 1368.0 * V / dt / 1e9),
                "seconds_per_apply": dt}
+        # one host thread on the same apply; the 4^4 configuration's M apply
+        # (median of 10) and CGNR solve to 1e-10, the 16^3 x 32 M apply
+        # (median of 3), all threads
+        oracle.set_threads(1)
+        t = time.perf_counter()
+        oracle.mop(U, b, dims, kappa)
+        cpu["seconds_per_apply_1_core"] = time.perf_counter() - t
+        oracle.set_threads(ncores)
+        small_cpu = {}
+        for name, d, kap, field, reps, solve in (
+                ("4^4", (4, 4, 4, 4), 0.12, synth.gauge_haar((4, 4, 4, 4), 0), 10, True),
+                ("16^3x32", (16, 16, 16, 32), 0.15, synth.gauge_smooth((16, 16, 16, 32), 0.30, 0),
+                 3, False)):
+            src = synth.gaussian_spinor(d, 1)
+            ts = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                oracle.mop(field, src, d, kap)
+                ts.append(time.perf_counter() - t)
+            small_cpu[name] = {"M_apply_us": 1e6 * float(np.median(ts))}
+            if solve:
+                t = time.perf_counter()
+                _, ost = oracle.cgnr(field, src, d, kap, tol=1e-10)
+                small_cpu[name].update({"cgnr_seconds": time.perf_counter() - t,
+                                        "cgnr_iterations": ost["iterations"],
+                                        "cgnr_true_res": ost["true_res"]})
+        cpu["small_configs"] = small_cpu
+        cpu["not_timed"] = ("the oracle's solves at 16^3x32 and %s (CGNR, 300-500 iterations "
+                            "of two full-lattice applies: tens of seconds to minutes of CPU)"
+                            % args.workload)
 
     out = {
         "metric": "Dslash GB/s (% HBM peak) & GFLOP/s; solves/s + p99 latency, mixed vs FP64",
