@@ -13,8 +13,8 @@ Printed: one JSON line. ``value`` is the whole-step throughput in algorithmic
 divided by the step's wall time. ``roofline`` describes the dominant kernel
 (the FP32 even-odd hopping term) timed with HIP events on the stream it runs
 on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice
-(all host threads, and one), and on the small configurations (with the 4^4
-CGNR solve).
+(all host threads, and one), and the M apply and CGNR solve of the two small
+configurations.
 Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
 the same solve with FP16-storage inner iterations, both mixed solves with
 12-real link storage, every Dslash variant's GB/s
@@ -668,9 +668,9 @@ def main():
                          "%.2f GFLOP/s at 1368 flop/site; GB/s counts 960 B/site like the "
                          "GPU M" % (nrep, args.workload, dt, 1368.0 * V / dt / 1e9),
                "seconds_per_apply": dt}
-        # one host thread on the same apply; the 4^4 configuration's M apply
-        # (median of 10) and CGNR solve to 1e-10, the 16^3 x 32 M apply
-        # (median of 3), all threads
+        # one host thread on the same apply; the M apply of the 4^4 and
+        # 16^3 x 32 configurations (median of 10 / 3) and their CGNR solves to
+        # 1e-10 (about 5 s of host time at 16^3 x 32), all threads
         oracle.set_threads(1)
         t = time.perf_counter()
         oracle.mop(U, b, dims, kappa)
@@ -680,7 +680,7 @@ def main():
         for name, d, kap, field, reps, solve in (
                 ("4^4", (4, 4, 4, 4), 0.12, synth.gauge_haar((4, 4, 4, 4), 0), 10, True),
                 ("16^3x32", (16, 16, 16, 32), 0.15, synth.gauge_smooth((16, 16, 16, 32), 0.30, 0),
-                 3, False)):
+                 3, True)):
             src = synth.gaussian_spinor(d, 1)
             ts = []
             for _ in range(reps):
@@ -695,9 +695,8 @@ def main():
                                         "cgnr_iterations": ost["iterations"],
                                         "cgnr_true_res": ost["true_res"]})
         cpu["small_configs"] = small_cpu
-        cpu["not_timed"] = ("the oracle's solves at 16^3x32 and %s (CGNR, 300-500 iterations "
-                            "of two full-lattice applies: tens of seconds to minutes of CPU)"
-                            % args.workload)
+        cpu["not_timed"] = ("the oracle's solve at %s (CGNR, about 500 iterations of two "
+                            "full-lattice applies: minutes of CPU)" % args.workload)
 
     out = {
         "metric": "Dslash GB/s (% HBM peak) & GFLOP/s; solves/s + p99 latency, mixed vs FP64",
