@@ -670,7 +670,7 @@ def main():
                "seconds_per_apply": dt}
         # one host thread on the same apply; the M apply of the 4^4 and
         # 16^3 x 32 configurations (median of 10 / 3) and their CGNR solves to
-        # 1e-10 (about 5 s of host time at 16^3 x 32), all threads
+        # 1e-10 (about 10 s of host time at 16^3 x 32), all threads
         oracle.set_threads(1)
         t = time.perf_counter()
         oracle.mop(U, b, dims, kappa)
