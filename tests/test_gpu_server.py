@@ -175,3 +175,26 @@ def test_merged_batches(w, fields):
         for U, b, p in reqs:
             x = gu.to_np(w.unpack_spinor(p.x, p.dims))
             assert oracle.true_residual(U, b, x, p.dims, 0.13) <= 1e-10
+
+
+def test_merged_batch_with_initial_guess(w, fields):
+    """WL_X0 through merged batches: each request starts from its own x (the
+    exact solution of one request needs no iteration, a zero x solves from
+    scratch), and the results meet the bound."""
+    dims = (4, 4, 4, 8)
+    U, G, _ = fields[dims]
+    flags = 0x20 | 0x40
+    srcs = [synth.gaussian_spinor(dims, 500 + i) for i in range(5)]
+    xs = [w.zeros_spinor(dims) for _ in srcs]
+    exact = w.zeros_spinor(dims)
+    st0 = w.solve_cg(G, w.pack_spinor(srcs[2], dims), exact, dims, 0.14, flags=flags)
+    assert st0["status"] == 0
+    xs[2].copy_(exact)
+    ps = [w.Problem(dims, 0.14, G, w.pack_spinor(b, dims), x) for b, x in zip(srcs, xs)]
+    with w.Server(hbm_budget=4 << 30, slots=1, flags=flags | 0x80, merge=8) as srv:
+        res = [srv.wait(t) for t in [srv.submit(p) for p in ps]]
+    assert res[2][1]["iterations"] == 0
+    for (code, st, tm), b, p in zip(res, srcs, ps):
+        assert code == 0
+        x = gu.to_np(w.unpack_spinor(p.x, dims))
+        assert oracle.true_residual(U, b, x, dims, 0.14) <= 1e-10
