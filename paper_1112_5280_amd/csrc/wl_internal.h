@@ -112,6 +112,15 @@ template <typename ST, int NCL> constexpr int link_cw() {
     return std::is_same<ST, double>::value ? 1 : (std::is_same<ST, float>::value ? 2 : 4);
 }
 
+// Streaming (non-temporal) load of device memory through a global
+// address-space pointer: a generic pointer would make it a flat load, which
+// also occupies the scalar-memory wait counter.
+template <typename T>
+__device__ __forceinline__ T load_nt(const T *p) {
+    typedef __attribute__((address_space(1))) const T GT;
+    return __builtin_nontemporal_load((GT *)p);
+}
+
 // NC complex numbers of site i: NC / CW arrays of S chunks of CW complex, then
 // (if NC % CW != 0) one array of S chunks holding the remaining NC % CW.
 // NT: read-once data (a streaming load that L2 need not keep).
@@ -124,7 +133,7 @@ __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Re
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         T c;
-        if constexpr (NT) c = __builtin_nontemporal_load(&p[j * S + i]);
+        if constexpr (NT) c = load_nt(&p[j * S + i]);
         else c = p[j * S + i];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
@@ -136,7 +145,7 @@ __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Re
         using TT = typename Vec<ST, TL>::T;
         const TT *q = reinterpret_cast<const TT *>(p + size_t(NF) * S) + i;
         TT c;
-        if constexpr (NT) c = __builtin_nontemporal_load(q);
+        if constexpr (NT) c = load_nt(q);
         else c = *q;
 #pragma unroll
         for (int k = 0; k < TL; ++k) {
@@ -196,7 +205,7 @@ __device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<R
         const float *sp = reinterpret_cast<const float *>(static_cast<const char *>(blk) +
                                                           size_t(S) * 48) + i;
         float s;
-        if constexpr (NT) s = __builtin_nontemporal_load(sp);
+        if constexpr (NT) s = load_nt(sp);
         else s = *sp;
 #pragma unroll
         for (int k = 0; k < 12; ++k) v[k] = s * v[k];
