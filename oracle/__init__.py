@@ -41,6 +41,8 @@ PINS = {
                        "block elimination",
     "cgnr/bicgstab": "LAPACK dense solve on 4^4; Neumann series for "
                      "kappa < 1/8; free-field plane-wave source",
+    "cgnr_eo": "LAPACK dense solve on 4^4 and 2x4x2x4; the odd rows of M x = b "
+               "hold exactly; free-field plane-wave source",
     "plaquette": "unit links give 1; gauge invariance",
     "singular_extremes": "LAPACK singular values of the dense operator on "
                          "2x4x2x4; free-field closed form min/max |lambda(p)|",
@@ -114,7 +116,7 @@ class Oracle:
         lib.orc_schur.argtypes = [P, P, P, P, P, D, I, I]
         lib.orc_plaquette.argtypes = [P, P]
         lib.orc_plaquette.restype = D
-        for fn in (lib.orc_cgnr, lib.orc_bicgstab):
+        for fn in (lib.orc_cgnr, lib.orc_cgnr_eo, lib.orc_bicgstab):
             fn.argtypes = [P, P, P, P, P, D, D, I, ctypes.POINTER(OrcStats)]
             fn.restype = I
         self.lib = lib
@@ -229,6 +231,15 @@ class Oracle:
         return self._solve(self.lib.orc_cgnr, U, b, dims, kappa, tol, maxiter,
                            phases, x0)
 
+    def cgnr_eo(self, U, b, dims, kappa, tol=1e-10, maxiter=100000,
+                phases=ANTIPERIODIC_T, x0=None):
+        """Solve M x = b by CG on the even-odd Schur system
+        Mhat^dag Mhat x_e = Mhat^dag (b_e + kappa D_eo b_o), then
+        x_o = b_o + kappa D_oe x_e; acceptance on the full residual.
+        Returns ``(x, stats)``."""
+        return self._solve(self.lib.orc_cgnr_eo, U, b, dims, kappa, tol, maxiter,
+                           phases, x0)
+
     def bicgstab(self, U, b, dims, kappa, tol=1e-10, maxiter=100000,
                  phases=ANTIPERIODIC_T, x0=None):
         """Solve M x = b by BiCGStab on M; returns ``(x, stats)``."""
@@ -300,7 +311,7 @@ def _forward(name):
 
 for _name in ("set_threads", "max_threads", "gamma", "dslash", "mop",
               "mop_sites", "dslash_sites", "dslash_eo", "schur", "plaquette",
-              "cgnr", "bicgstab", "true_residual", "singular_extremes"):
+              "cgnr", "cgnr_eo", "bicgstab", "true_residual", "singular_extremes"):
     globals()[_name] = _forward(_name)
 
 

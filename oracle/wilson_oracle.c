@@ -315,13 +315,13 @@ void orc_dslash_eo(const cplx *U, const cplx *psi, cplx *out, const int L[4],
 /*
  * Schur complement on parity p:  Mhat = 1 - kappa^2 D_{p,1-p} D_{1-p,p}
  * (dagger: g5 Mhat g5). Whole-lattice arrays; output is zero on parity 1-p.
+ * tmp and tmp2 are whole-lattice scratch arrays.
  */
-void orc_schur(const cplx *U, const cplx *psi, cplx *out, const int L[4],
-               const cplx ph[4], double kappa, int parity, int dagger)
+static void schur_into(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+                       const cplx ph[4], double kappa, int parity, int dagger,
+                       cplx *tmp, cplx *tmp2)
 {
     long V = volume4(L);
-    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 12 * V);
-    cplx *tmp2 = (cplx *)malloc(sizeof(cplx) * 12 * V);
     orc_dslash_eo(U, psi, tmp, L, ph, 1 - parity, dagger);
     orc_dslash_eo(U, tmp, tmp2, L, ph, parity, dagger);
 #pragma omp parallel for schedule(static)
@@ -333,6 +333,15 @@ void orc_schur(const cplx *U, const cplx *psi, cplx *out, const int L[4],
                                   ? psi[s * 12 + k] - kappa * kappa * tmp2[s * 12 + k]
                                   : 0.0;
     }
+}
+
+void orc_schur(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+               const cplx ph[4], double kappa, int parity, int dagger)
+{
+    long V = volume4(L);
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    cplx *tmp2 = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    schur_into(U, psi, out, L, ph, kappa, parity, dagger, tmp, tmp2);
     free(tmp);
     free(tmp2);
 }
@@ -467,6 +476,91 @@ int orc_cgnr(const cplx *U, const cplx *b, cplx *x, const int L[4],
     }
     if (st) { st->iterations = it; st->restarts = restarts; st->true_res = rho; }
     free(r); free(p); free(t); free(q);
+    return status;
+}
+
+/*
+ * Even-odd CGNR: the same Hestenes-Stiefel CG, run on the Schur system of the
+ * even sites (paper Sec. 3, even-odd preconditioning). With
+ *   Mhat = 1 - kappa^2 D_eo D_oe   and   bhat_e = b_e + kappa D_eo b_o,
+ * CG solves Mhat^dag Mhat x_e = Mhat^dag bhat_e from x_e (the even part of x
+ * on entry); the odd part then follows exactly from the odd rows of M x = b:
+ *   x_o = b_o + kappa D_oe x_e.
+ * Stopping and restarts as in orc_cgnr: the CG loop stops when
+ * ||r_k|| <= eta ||Mhat^dag bhat_e||, the true residual ||b - M x|| / ||b|| of
+ * the full system is recomputed, and CG restarts from x_e with
+ * eta <- eta (tol / rho) / 2 until rho <= tol. Same return codes as orc_cgnr.
+ * All arrays are whole-lattice; the Krylov vectors are zero on odd sites.
+ */
+int orc_cgnr_eo(const cplx *U, const cplx *b, cplx *x, const int L[4],
+                const cplx ph[4], double kappa, double tol, int maxiter,
+                orc_stats *st)
+{
+    long V = volume4(L), n = V * 12;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *t = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    cplx *bh = malloc(sizeof(cplx) * n), *xe = malloc(sizeof(cplx) * n);
+    cplx *w1 = malloc(sizeof(cplx) * n), *w2 = malloc(sizeof(cplx) * n);
+    char *even = malloc(V);
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        even[s] = parity_of(c) == 0;
+    }
+    double bnorm = sqrt(vnorm2(b, n));
+    /* bhat_e = b_e + kappa D_eo b  (only the odd part of b enters D_eo) */
+    orc_dslash_eo(U, b, w1, L, ph, 0, 0);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) bh[i] = even[i / 12] ? b[i] + kappa * w1[i] : 0.0;
+    schur_into(U, bh, t, L, ph, kappa, 0, 1, w1, w2);
+    double mbnorm = sqrt(vnorm2(t, n));
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) xe[i] = even[i / 12] ? x[i] : 0.0;
+    double eta = tol;
+    int it = 0, restarts = 0, status = 1;
+    double rho = 1.0;
+    for (;;) {
+        /* r = Mhat^dag (bhat - Mhat x_e); p = r */
+        schur_into(U, xe, t, L, ph, kappa, 0, 0, w1, w2);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) t[i] = bh[i] - t[i];
+        schur_into(U, t, r, L, ph, kappa, 0, 1, w1, w2);
+        memcpy(p, r, sizeof(cplx) * n);
+        double rr = vnorm2(r, n);
+        while (rr > eta * eta * mbnorm * mbnorm && it < maxiter) {
+            schur_into(U, p, t, L, ph, kappa, 0, 0, w1, w2);
+            double pap = vnorm2(t, n);
+            if (!(pap > 0.0) || !isfinite(pap)) break;
+            double alpha = rr / pap;
+            schur_into(U, t, q, L, ph, kappa, 0, 1, w1, w2);
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) {
+                xe[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            double rr_new = vnorm2(r, n);
+            double beta = rr_new / rr;
+            rr = rr_new;
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+            ++it;
+        }
+        /* x = (x_e, b_o + kappa D_oe x_e) */
+        orc_dslash_eo(U, xe, w1, L, ph, 1, 0);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) x[i] = even[i / 12] ? xe[i] : b[i] + kappa * w1[i];
+        orc_mop(U, x, t, L, ph, kappa, 0);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+        rho = sqrt(vnorm2(t, n)) / bnorm;
+        if (!isfinite(rho)) { status = 2; break; }
+        if (rho <= tol) { status = 0; break; }
+        if (it >= maxiter || restarts >= ORC_MAX_RESTARTS) { status = 1; break; }
+        eta = eta * (tol / rho) * 0.5;
+        ++restarts;
+    }
+    if (st) { st->iterations = it; st->restarts = restarts; st->true_res = rho; }
+    free(r); free(p); free(t); free(q); free(bh); free(xe); free(w1); free(w2); free(even);
     return status;
 }
 

@@ -251,7 +251,7 @@ def pin_solvers_lapack(orc, dims=(4, 4, 4, 4), kappa=0.12, maxiter=3000):
     # system the recursive residual tracks the true one to rounding, so a
     # correct method needs at most a couple of true-residual restarts.
     it_bound = cond * np.log(2 / 1e-10) / 2
-    for solver in (orc.cgnr, orc.bicgstab):
+    for solver in (orc.cgnr, orc.cgnr_eo, orc.bicgstab):
         x, st = solver(U, b, dims, kappa, tol=1e-10, maxiter=maxiter)
         assert st["status"] == 0, st
         res = np.linalg.norm(b.reshape(-1) - M @ x.reshape(-1)) / np.linalg.norm(b)
@@ -288,10 +288,29 @@ def pin_free_field_solve(orc, dims=(4, 2, 4, 8), kappa=0.12):
     lam, vec = np.linalg.eig(A)
     w = np.outer(vec[:, 0], np.array([0.3, -1.0j, 0.7]))
     b = _plane_wave(dims, p)[:, None, None] * w[None]
-    for solver in (orc.cgnr, orc.bicgstab):
+    for solver in (orc.cgnr, orc.cgnr_eo, orc.bicgstab):
         x, st = solver(U, b, dims, kappa, tol=1e-12, maxiter=3000)
         assert st["status"] == 0
         assert rel(x, b / lam[0]) < 1e-10
+
+
+def pin_eo_solve_odd_rows(orc, dims=(4, 2, 4, 6), kappa=0.13):
+    """The even-odd solve fixes x_o from x_e through the odd rows of M x = b,
+    so those rows hold to rounding whatever x_e is; and its solution agrees
+    with LAPACK's dense solve of the full system within cond * tol."""
+    U = synth.gauge_smooth(dims, 0.3, 31)
+    b = synth.gaussian_spinor(dims, 32)
+    V = int(np.prod(dims))
+    _, odd = parity_index(dims)
+    for tol, maxiter in ((1e-2, 3000), (1e-12, 3000)):
+        x, st = orc.cgnr_eo(U, b, dims, kappa, tol=tol, maxiter=maxiter)
+        r = (b - orc.mop(U, x, dims, kappa)).reshape(-1)
+        assert np.linalg.norm(r[odd]) <= 1e-14 * np.linalg.norm(b), tol
+        assert st["status"] == 0 and st["true_res"] <= tol, st
+    D = dense_dslash(U, dims, gammas(orc), AP)
+    M = np.eye(12 * V) - kappa * D
+    xs = np.linalg.solve(M, b.reshape(-1))
+    assert rel(x.reshape(-1), xs) <= np.linalg.cond(M) * 2e-12
 
 
 def pin_plaquette(orc, dims=(4, 4, 2, 4)):
@@ -341,6 +360,6 @@ ALL_PINS = [
     pin_gamma_algebra, pin_free_field_plane_wave, pin_free_field_spectrum,
     pin_dense_kron, pin_gamma5_hermiticity, pin_gauge_covariance,
     pin_eo_split, pin_schur_dense, pin_sites, pin_solvers_lapack,
-    pin_neumann, pin_free_field_solve, pin_plaquette,
+    pin_neumann, pin_free_field_solve, pin_eo_solve_odd_rows, pin_plaquette,
     pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]

@@ -55,6 +55,13 @@ MUTANTS = [
     ("cg beta inverted", "double beta = rr_new / rr;", "double beta = rr / rr_new;"),
     ("bicgstab x misses omega s", "x[i] += alpha * p[i] + omega * s[i];",
      "x[i] += alpha * p[i];"),
+    ("eo source sign", "bh[i] = even[i / 12] ? b[i] + kappa * w1[i] : 0.0;",
+     "bh[i] = even[i / 12] ? b[i] - kappa * w1[i] : 0.0;"),
+    ("eo reconstruction sign", "x[i] = even[i / 12] ? xe[i] : b[i] + kappa * w1[i];",
+     "x[i] = even[i / 12] ? xe[i] : b[i] - kappa * w1[i];"),
+    ("eo normal equations without the adjoint",
+     "        schur_into(U, p, t, L, ph, kappa, 0, 0, w1, w2);\n            double pap",
+     "        schur_into(U, p, t, L, ph, kappa, 0, 1, w1, w2);\n            double pap"),
     ("plaquette misses a conjugate",
      "acc += ab[i * 3 + k] * conj(e[j * 3 + k]);",
      "acc += ab[i * 3 + k] * e[j * 3 + k];"),
