@@ -41,6 +41,9 @@ PINS = {
                        "block elimination",
     "cgnr/bicgstab": "LAPACK dense solve on 4^4; Neumann series for "
                      "kappa < 1/8; free-field plane-wave source",
+    "mop_tm/cgnr_tm": "free-field eigenvalues 1 - 2k sum cos p +- 2ik sqrt(mu^2 + "
+                      "sum sin^2 p); g5 M(mu) g5 = M(-mu)^dag; mu = 0 is M; dense "
+                      "2x4x2x4 with the twist; LAPACK solve",
     "cgnr_eo": "LAPACK dense solve on 4^4 and 2x4x2x4; the odd rows of M x = b "
                "hold exactly; free-field plane-wave source",
     "plaquette": "unit links give 1; gauge invariance",
@@ -110,10 +113,15 @@ class Oracle:
         lib.orc_set_threads.argtypes = [I]
         lib.orc_dslash.argtypes = [P, P, P, P, P, I]
         lib.orc_mop.argtypes = [P, P, P, P, P, D, I]
+        lib.orc_mop_tm.argtypes = [P, P, P, P, P, D, D, I]
+        lib.orc_cgnr_tm.argtypes = [P, P, P, P, P, D, D, D, I, ctypes.POINTER(OrcStats)]
+        lib.orc_cgnr_tm.restype = I
         lib.orc_mop_sites.argtypes = [P, P, P, P, D, I, P, ctypes.c_long, P]
         lib.orc_dslash_sites.argtypes = [P, P, P, P, I, P, ctypes.c_long, P]
         lib.orc_dslash_eo.argtypes = [P, P, P, P, P, I, I]
         lib.orc_schur.argtypes = [P, P, P, P, P, D, I, I]
+        lib.orc_lanczos_mdm.argtypes = [P, P, P, P, D, I, P, P]
+        lib.orc_lanczos_mdm.restype = I
         lib.orc_plaquette.argtypes = [P, P]
         lib.orc_plaquette.restype = D
         for fn in (lib.orc_cgnr, lib.orc_cgnr_eo, lib.orc_bicgstab):
@@ -156,6 +164,34 @@ class Oracle:
         self.lib.orc_mop(_ptr(U), _ptr(psi), _ptr(out), _ptr(d), _ptr(ph),
                          float(kappa), int(dagger))
         return out
+
+    def mop_tm(self, U, psi, dims, kappa, mu, phases=ANTIPERIODIC_T, dagger=False):
+        """Twisted-mass operator M(mu) psi = psi + 2 i kappa mu g5 psi - kappa D_W psi;
+        ``dagger`` gives M(mu)^dag = g5 M(-mu) g5."""
+        d, U, psi = self._fields(U, psi, dims)
+        out = np.empty_like(psi)
+        ph = _phases(phases)
+        self.lib.orc_mop_tm(_ptr(U), _ptr(psi), _ptr(out), _ptr(d), _ptr(ph),
+                            float(kappa), float(mu), int(dagger))
+        return out
+
+    def cgnr_tm(self, U, b, dims, kappa, mu, tol=1e-10, maxiter=100000,
+                phases=ANTIPERIODIC_T, x0=None):
+        """Solve M(mu) x = b by CGNR; returns ``(x, stats)``."""
+        d, U, b = self._fields(U, b, dims)
+        x = np.zeros_like(b) if x0 is None else _c128(x0, b.shape).copy()
+        ph = _phases(phases)
+        st = OrcStats()
+        status = self.lib.orc_cgnr_tm(_ptr(U), _ptr(b), _ptr(x), _ptr(d), _ptr(ph),
+                                      float(kappa), float(mu), float(tol), int(maxiter),
+                                      ctypes.byref(st))
+        return x, dict(status=int(status), iterations=int(st.iterations),
+                       restarts=int(st.restarts), true_res=float(st.true_res))
+
+    def true_residual_tm(self, U, b, x, dims, kappa, mu, phases=ANTIPERIODIC_T):
+        """||b - M(mu) x|| / ||b|| with the oracle's FP64 twisted-mass operator."""
+        r = _c128(b) - self.mop_tm(U, x, dims, kappa, mu, phases)
+        return float(np.linalg.norm(r) / np.linalg.norm(b))
 
     def _sites(self, sites, v):
         s = np.ascontiguousarray(np.asarray(sites, dtype=np.int64).reshape(-1))
@@ -267,26 +303,17 @@ class Oracle:
         cond is an underestimate. Returns ``(sigma_max, sigma_min, cond)``.
         """
         d = _dims(dims)
+        U = _c128(U, (_vol(d), 4, 3, 3))
         shape = (_vol(d), 4, 3)
         rng = np.random.default_rng(seed)
         v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
-        v /= np.linalg.norm(v)
-        v_prev = np.zeros_like(v)
-        alpha, beta = [], []
-        b_prev = 0.0
-        for _ in range(steps):
-            w = self.mop(U, self.mop(U, v, dims, kappa, phases), dims, kappa,
-                         phases, dagger=True)
-            a = float(np.vdot(v, w).real)
-            w = w - a * v - b_prev * v_prev
-            alpha.append(a)
-            b = float(np.linalg.norm(w))
-            if b <= 1e-13 * abs(a):     # invariant subspace: T is exact
-                break
-            beta.append(b)
-            v_prev, v, b_prev = v, w / b, b
-        k = len(alpha)
-        T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+        v = np.ascontiguousarray(v / np.linalg.norm(v))
+        alpha = np.zeros(steps)
+        beta = np.zeros(max(steps - 1, 1))
+        ph = _phases(phases)
+        k = int(self.lib.orc_lanczos_mdm(_ptr(U), _ptr(v), _ptr(d), _ptr(ph), float(kappa),
+                                         int(steps), _ptr(alpha), _ptr(beta)))
+        T = np.diag(alpha[:k]) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
         ev = np.linalg.eigvalsh(T)
         smax, smin = float(np.sqrt(ev[-1])), float(np.sqrt(max(ev[0], 0.0)))
         return smax, smin, smax / smin
@@ -311,7 +338,7 @@ def _forward(name):
 
 for _name in ("set_threads", "max_threads", "gamma", "dslash", "mop",
               "mop_sites", "dslash_sites", "dslash_eo", "schur", "plaquette",
-              "cgnr", "cgnr_eo", "bicgstab", "true_residual", "singular_extremes"):
+              "cgnr", "cgnr_eo", "bicgstab", "mop_tm", "cgnr_tm", "true_residual_tm", "true_residual", "singular_extremes"):
     globals()[_name] = _forward(_name)
 
 

@@ -229,6 +229,26 @@ static void mop_site(const cplx *U, const cplx *psi, const int L[4],
         memcpy(out, m, sizeof m);
 }
 
+/*
+ * Twisted-mass Wilson operator of one flavour (paper Sec. 3: the group's
+ * N_f = 2 twisted-mass Wilson fermions; the two flavours carry +mu and -mu):
+ *   M(mu) = 1 + 2 i kappa mu gamma5 - kappa D_W,
+ * and its adjoint M(mu)^dag = 1 - 2 i kappa mu gamma5 - kappa D_W^dag
+ * = gamma5 M(-mu) gamma5. The twist is added to the Wilson site operator.
+ */
+static void mop_tm_site(const cplx *U, const cplx *psi, const int L[4],
+                        const cplx ph[4], double kappa, double mu, int dagger, long s,
+                        cplx out[4][3])
+{
+    cplx w[4][3], raw[4][3], g5psi[4][3];
+    mop_site(U, psi, L, ph, kappa, dagger, s, w);
+    memcpy(raw, psi + s * 12, sizeof raw);
+    spin_apply(GAM5, raw, g5psi);
+    double tw = dagger ? -2.0 * kappa * mu : 2.0 * kappa * mu;
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) out[a][i] = w[a][i] + I * tw * g5psi[a][i];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole-lattice operators (exported)                                        */
 /* ------------------------------------------------------------------------ */
@@ -257,6 +277,16 @@ void orc_mop(const cplx *U, const cplx *psi, cplx *out, const int L[4],
 #pragma omp parallel for schedule(static)
     for (long s = 0; s < V; ++s)
         mop_site(U, psi, L, ph, kappa, dagger, s, (cplx(*)[3])(out + s * 12));
+}
+
+/* out = M(mu) psi (dagger: M(mu)^dag psi), twisted-mass Wilson operator */
+void orc_mop_tm(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+                const cplx ph[4], double kappa, double mu, int dagger)
+{
+    long V = volume4(L);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s)
+        mop_tm_site(U, psi, L, ph, kappa, mu, dagger, s, (cplx(*)[3])(out + s * 12));
 }
 
 /* M (or M^dag) at a list of sites only: out[n][12]. */
@@ -480,6 +510,59 @@ int orc_cgnr(const cplx *U, const cplx *b, cplx *x, const int L[4],
 }
 
 /*
+ * CGNR for the twisted-mass operator: orc_cgnr's algorithm (CG on
+ * M^dag M x = M^dag b, true-residual restarts) with M = M(mu).
+ */
+int orc_cgnr_tm(const cplx *U, const cplx *b, cplx *x, const int L[4],
+                const cplx ph[4], double kappa, double mu, double tol, int maxiter,
+                orc_stats *st)
+{
+    long n = volume4(L) * 12;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *t = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    double bnorm = sqrt(vnorm2(b, n));
+    orc_mop_tm(U, b, t, L, ph, kappa, mu, 1);
+    double mbnorm = sqrt(vnorm2(t, n));
+    double eta = tol;
+    int it = 0, restarts = 0, status = 1;
+    double rho = 1.0;
+    for (;;) {
+        orc_mop_tm(U, x, t, L, ph, kappa, mu, 0);
+        for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+        orc_mop_tm(U, t, r, L, ph, kappa, mu, 1);
+        memcpy(p, r, sizeof(cplx) * n);
+        double rr = vnorm2(r, n);
+        while (rr > eta * eta * mbnorm * mbnorm && it < maxiter) {
+            orc_mop_tm(U, p, t, L, ph, kappa, mu, 0);
+            double pap = vnorm2(t, n);
+            if (!(pap > 0.0) || !isfinite(pap)) break;
+            double alpha = rr / pap;
+            orc_mop_tm(U, t, q, L, ph, kappa, mu, 1);
+            for (long i = 0; i < n; ++i) {
+                x[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            double rr_new = vnorm2(r, n);
+            double beta = rr_new / rr;
+            rr = rr_new;
+            for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+            ++it;
+        }
+        orc_mop_tm(U, x, t, L, ph, kappa, mu, 0);
+        for (long i = 0; i < n; ++i) t[i] = b[i] - t[i];
+        rho = sqrt(vnorm2(t, n)) / bnorm;
+        if (!isfinite(rho)) { status = 2; break; }
+        if (rho <= tol) { status = 0; break; }
+        if (it >= maxiter || restarts >= ORC_MAX_RESTARTS) { status = 1; break; }
+        eta = eta * (tol / rho) * 0.5;
+        ++restarts;
+    }
+    if (st) { st->iterations = it; st->restarts = restarts; st->true_res = rho; }
+    free(r); free(p); free(t); free(q);
+    return status;
+}
+
+/*
  * Even-odd CGNR: the same Hestenes-Stiefel CG, run on the Schur system of the
  * even sites (paper Sec. 3, even-odd preconditioning). With
  *   Mhat = 1 - kappa^2 D_eo D_oe   and   bhat_e = b_e + kappa D_eo b_o,
@@ -562,6 +645,45 @@ int orc_cgnr_eo(const cplx *U, const cplx *b, cplx *x, const int L[4],
     if (st) { st->iterations = it; st->restarts = restarts; st->true_res = rho; }
     free(r); free(p); free(t); free(q); free(bh); free(xe); free(w1); free(w2); free(even);
     return status;
+}
+
+/*
+ * Plain Lanczos tridiagonalisation of A = M^dag M from the unit start vector
+ * v (overwritten), no reorthogonalisation: for k = 0, 1, ...
+ *   w = A v_k - beta_{k-1} v_{k-1},  alpha_k = <v_k, w>,  w -= alpha_k v_k,
+ *   beta_k = ||w||,  v_{k+1} = w / beta_k.
+ * alpha[0..n) and beta[0..n-1) receive the tridiagonal matrix T (n returned,
+ * n <= steps; it stops early when beta_k <= 1e-13 |alpha_k|, an invariant
+ * subspace, where T is exact). The extreme eigenvalues of T approximate
+ * sigma_max^2 and sigma_min^2 of M from inside the spectrum.
+ */
+int orc_lanczos_mdm(const cplx *U, cplx *v, const int L[4], const cplx ph[4],
+                    double kappa, int steps, double *alpha, double *beta)
+{
+    long n = volume4(L) * 12;
+    cplx *vp = calloc(n, sizeof(cplx)), *t = malloc(sizeof(cplx) * n);
+    cplx *w = malloc(sizeof(cplx) * n);
+    double bprev = 0.0;
+    int k = 0;
+    for (; k < steps; ++k) {
+        orc_mop(U, v, t, L, ph, kappa, 0);
+        orc_mop(U, t, w, L, ph, kappa, 1);
+        double a = creal(vdot(v, w, n));
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) w[i] = w[i] - a * v[i] - bprev * vp[i];
+        alpha[k] = a;
+        double bk = sqrt(vnorm2(w, n));
+        if (bk <= 1e-13 * fabs(a)) { ++k; break; }
+        if (k + 1 < steps) beta[k] = bk;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            vp[i] = v[i];
+            v[i] = w[i] / bk;
+        }
+        bprev = bk;
+    }
+    free(vp); free(t); free(w);
+    return k;
 }
 
 /*

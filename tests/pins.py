@@ -313,6 +313,67 @@ def pin_eo_solve_odd_rows(orc, dims=(4, 2, 4, 6), kappa=0.13):
     assert rel(x.reshape(-1), xs) <= np.linalg.cond(M) * 2e-12
 
 
+def _g5_dense(orc, V):
+    """gamma_5 = gamma_x gamma_y gamma_z gamma_t on every site and colour."""
+    g = gammas(orc)
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    return np.kron(np.eye(V), np.kron(g5, np.eye(3)))
+
+
+def pin_tm_free_field_spectrum(orc, dims=(2, 4, 2, 4), kappa=0.13, mu=0.37):
+    """Unit links: the 12V eigenvalues of M(mu) = 1 + 2ik mu g5 - k D_W are
+    1 - 2k sum cos p +- 2ik sqrt(mu^2 + sum sin^2 p), each 6-fold (g5
+    anticommutes with every gamma_mu, so (mu g5 + sum sin p gamma)^2 is
+    mu^2 + sum sin^2 p)."""
+    V = int(np.prod(dims))
+    U = synth.gauge_unit(dims)
+    M = _dense_from_apply(
+        lambda e: orc.mop_tm(U, e.reshape(V, 4, 3), dims, kappa, mu, AP).reshape(-1),
+        12 * V)
+    ev = np.linalg.eigvals(M)
+    mom = _momenta(dims, AP)
+    want = []
+    for n in itertools.product(*[range(d) for d in dims]):
+        p = [mom[m][n[m]] for m in range(4)]
+        c = 1 - 2 * kappa * sum(np.cos(p))
+        s2 = np.sqrt(mu * mu + sum(np.sin(x) ** 2 for x in p))
+        want += [c + 2j * kappa * s2] * 6 + [c - 2j * kappa * s2] * 6
+    assert _sorted_close(ev, np.array(want), 1e-10), "twisted free-field spectrum"
+
+
+def pin_tm_dense_and_adjoint(orc, dims=(2, 4, 2, 4), seed=41, kappa=0.12, mu=0.21):
+    """M(mu) equals the dense Kronecker-assembled 1 - k D_W + 2ik mu g5, its
+    adjoint is the conjugate transpose, g5 M(mu) g5 = M(-mu)^dag, and mu = 0 is
+    the Wilson operator."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, seed)
+    D = dense_dslash(U, dims, gammas(orc), AP)
+    G5 = _g5_dense(orc, V)
+    M = np.eye(12 * V) - kappa * D + 2j * kappa * mu * G5
+    psi = synth.gaussian_spinor(dims, seed + 1)
+    v = psi.reshape(-1)
+    assert rel(orc.mop_tm(U, psi, dims, kappa, mu).reshape(-1), M @ v) < 1e-13
+    assert rel(orc.mop_tm(U, psi, dims, kappa, mu, dagger=True).reshape(-1),
+               M.conj().T @ v) < 1e-13
+    g5m = (G5 @ orc.mop_tm(U, (G5 @ v).reshape(V, 4, 3), dims, kappa, -mu).reshape(-1))
+    assert rel(g5m, orc.mop_tm(U, psi, dims, kappa, mu, dagger=True).reshape(-1)) < 1e-13
+    assert rel(orc.mop_tm(U, psi, dims, kappa, 0.0), orc.mop(U, psi, dims, kappa)) < 1e-15
+
+
+def pin_tm_solve_lapack(orc, dims=(2, 4, 2, 4), kappa=0.12, mu=0.15):
+    """CGNR on M(mu) reaches LAPACK's solution of the dense twisted system."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, 43)
+    b = synth.gaussian_spinor(dims, 44)
+    M = np.eye(12 * V) - kappa * dense_dslash(U, dims, gammas(orc), AP) + \
+        2j * kappa * mu * _g5_dense(orc, V)
+    xs = np.linalg.solve(M, b.reshape(-1))
+    x, st = orc.cgnr_tm(U, b, dims, kappa, mu, tol=1e-11, maxiter=3000)
+    assert st["status"] == 0, st
+    assert rel(x.reshape(-1), xs) <= np.linalg.cond(M) * 2e-11
+    assert abs(orc.true_residual_tm(U, b, x, dims, kappa, mu) - st["true_res"]) < 1e-13
+
+
 def pin_plaquette(orc, dims=(4, 4, 2, 4)):
     """Unit links give plaquette 1; the plaquette is gauge invariant."""
     assert abs(orc.plaquette(synth.gauge_unit(dims), dims) - 1.0) < 1e-15
@@ -361,5 +422,6 @@ ALL_PINS = [
     pin_dense_kron, pin_gamma5_hermiticity, pin_gauge_covariance,
     pin_eo_split, pin_schur_dense, pin_sites, pin_solvers_lapack,
     pin_neumann, pin_free_field_solve, pin_eo_solve_odd_rows, pin_plaquette,
+    pin_tm_free_field_spectrum, pin_tm_dense_and_adjoint, pin_tm_solve_lapack,
     pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]

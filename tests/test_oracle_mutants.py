@@ -62,6 +62,14 @@ MUTANTS = [
     ("eo normal equations without the adjoint",
      "        schur_into(U, p, t, L, ph, kappa, 0, 0, w1, w2);\n            double pap",
      "        schur_into(U, p, t, L, ph, kappa, 0, 1, w1, w2);\n            double pap"),
+    ("twist sign kept in the adjoint",
+     "double tw = dagger ? -2.0 * kappa * mu : 2.0 * kappa * mu;",
+     "double tw = 2.0 * kappa * mu;"),
+    ("twist without its factor 2",
+     "double tw = dagger ? -2.0 * kappa * mu : 2.0 * kappa * mu;",
+     "double tw = dagger ? -kappa * mu : kappa * mu;"),
+    ("twist misses gamma5", "out[a][i] = w[a][i] + I * tw * g5psi[a][i];",
+     "out[a][i] = w[a][i] + I * tw * raw[a][i];"),
     ("plaquette misses a conjugate",
      "acc += ab[i * 3 + k] * conj(e[j * 3 + k]);",
      "acc += ab[i * 3 + k] * e[j * 3 + k];"),
