@@ -44,6 +44,8 @@ PINS = {
     "mop_tm/cgnr_tm": "free-field eigenvalues 1 - 2k sum cos p +- 2ik sqrt(mu^2 + "
                       "sum sin^2 p); g5 M(mu) g5 = M(-mu)^dag; mu = 0 is M; dense "
                       "2x4x2x4 with the twist; LAPACK solve",
+    "meson": "pion channel -sum |S|^2; completeness of the 16 Gammas "
+             "(sum_n Gamma_n^2 C_n = -4 sum |Tr_spin S|^2); gauge invariance; time shift",
     "cgnr_eo": "LAPACK dense solve on 4^4 and 2x4x2x4; the odd rows of M x = b "
                "hold exactly; free-field plane-wave source",
     "plaquette": "unit links give 1; gauge invariance",
@@ -114,6 +116,7 @@ class Oracle:
         lib.orc_dslash.argtypes = [P, P, P, P, P, I]
         lib.orc_mop.argtypes = [P, P, P, P, P, D, I]
         lib.orc_mop_tm.argtypes = [P, P, P, P, P, D, D, I]
+        lib.orc_schur_tm.argtypes = [P, P, P, P, P, D, D, I, I]
         lib.orc_cgnr_tm.argtypes = [P, P, P, P, P, D, D, D, I, ctypes.POINTER(OrcStats)]
         lib.orc_cgnr_tm.restype = I
         lib.orc_mop_sites.argtypes = [P, P, P, P, D, I, P, ctypes.c_long, P]
@@ -122,6 +125,7 @@ class Oracle:
         lib.orc_schur.argtypes = [P, P, P, P, P, D, I, I]
         lib.orc_lanczos_mdm.argtypes = [P, P, P, P, D, I, P, P]
         lib.orc_lanczos_mdm.restype = I
+        lib.orc_meson.argtypes = [P, P, I, P]
         lib.orc_plaquette.argtypes = [P, P]
         lib.orc_plaquette.restype = D
         for fn in (lib.orc_cgnr, lib.orc_cgnr_eo, lib.orc_bicgstab):
@@ -173,6 +177,17 @@ class Oracle:
         ph = _phases(phases)
         self.lib.orc_mop_tm(_ptr(U), _ptr(psi), _ptr(out), _ptr(d), _ptr(ph),
                             float(kappa), float(mu), int(dagger))
+        return out
+
+    def schur_tm(self, U, psi, dims, kappa, mu, parity=0, phases=ANTIPERIODIC_T,
+                 dagger=False):
+        """Twisted-mass Schur complement S_p psi = A psi - kappa^2 D_{p,1-p} A^-1
+        D_{1-p,p} psi on parity p, A = 1 + 2 i kappa mu g5 (zero on parity 1-p)."""
+        d, U, psi = self._fields(U, psi, dims)
+        out = np.empty_like(psi)
+        ph = _phases(phases)
+        self.lib.orc_schur_tm(_ptr(U), _ptr(psi), _ptr(out), _ptr(d), _ptr(ph),
+                              float(kappa), float(mu), int(parity), int(dagger))
         return out
 
     def cgnr_tm(self, U, b, dims, kappa, mu, tol=1e-10, maxiter=100000,
@@ -243,6 +258,19 @@ class Oracle:
         ph = _phases(phases)
         self.lib.orc_schur(_ptr(U), _ptr(psi), _ptr(out), _ptr(d), _ptr(ph),
                            float(kappa), int(parity), int(dagger))
+        return out
+
+    def meson(self, props, dims, t0=0):
+        """Meson correlators of Eq. 1, C_Gamma(t) = -sum_xvec Tr(S^dag g5 Gamma S
+        Gamma g5), for the 16 Gamma_n = g_x^n0 g_y^n1 g_z^n2 g_t^n3 (bits of n),
+        t counted from t0. ``props`` is [12, V, 4, 3]: the solutions for the
+        point sources of spin b and colour c in row 3 b + c. Returns a complex
+        array [16, Lt]."""
+        d = _dims(dims)
+        v = _vol(d)
+        pr = _c128(props, (12, v, 4, 3))
+        out = np.zeros((16, int(d[3])), dtype=np.complex128)
+        self.lib.orc_meson(_ptr(pr), _ptr(d), int(t0), _ptr(out))
         return out
 
     def plaquette(self, U, dims) -> float:
@@ -338,7 +366,7 @@ def _forward(name):
 
 for _name in ("set_threads", "max_threads", "gamma", "dslash", "mop",
               "mop_sites", "dslash_sites", "dslash_eo", "schur", "plaquette",
-              "cgnr", "cgnr_eo", "bicgstab", "mop_tm", "cgnr_tm", "true_residual_tm", "true_residual", "singular_extremes"):
+              "cgnr", "cgnr_eo", "bicgstab", "mop_tm", "schur_tm", "cgnr_tm", "meson", "true_residual_tm", "true_residual", "singular_extremes"):
     globals()[_name] = _forward(_name)
 
 

@@ -376,6 +376,113 @@ void orc_schur(const cplx *U, const cplx *psi, cplx *out, const int L[4],
     free(tmp2);
 }
 
+/*
+ * Twisted-mass Schur complement on parity p, with A = 1 + 2 i kappa mu g5:
+ *   S_p = A - kappa^2 D_{p,1-p} A^-1 D_{1-p,p}
+ * (dagger: S_p^dag = A^dag - kappa^2 D^dag_{p,1-p} A^-dag D^dag_{1-p,p}, i.e.
+ * mu -> -mu with the adjoint hops). A^-1 is applied as the solution of the
+ * 4x4 spin system (1 + i t g5) y = v with t = 2 kappa mu, using the
+ * explicit gamma5: y = (1 - i t g5) v / (1 + t^2). Whole-lattice arrays;
+ * output is zero on parity 1-p.
+ */
+void orc_schur_tm(const cplx *U, const cplx *psi, cplx *out, const int L[4],
+                  const cplx ph[4], double kappa, double mu, int parity, int dagger)
+{
+    long V = volume4(L);
+    double t = (dagger ? -2.0 : 2.0) * kappa * mu;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    cplx *tmp2 = (cplx *)malloc(sizeof(cplx) * 12 * V);
+    orc_dslash_eo(U, psi, tmp, L, ph, 1 - parity, dagger);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        cplx g5v[4][3];
+        spin_apply(GAM5, (const cplx(*)[3])(tmp + s * 12), g5v);
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i)
+                tmp[s * 12 + a * 3 + i] = (tmp[s * 12 + a * 3 + i] - I * t * g5v[a][i]) / (1.0 + t * t);
+    }
+    orc_dslash_eo(U, tmp, tmp2, L, ph, parity, dagger);
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        cplx g5p[4][3];
+        spin_apply(GAM5, (const cplx(*)[3])(psi + s * 12), g5p);
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i) {
+                long k = s * 12 + a * 3 + i;
+                out[k] = (parity_of(c) == parity)
+                             ? psi[k] + I * t * g5p[a][i] - kappa * kappa * tmp2[k]
+                             : 0.0;
+            }
+    }
+    free(tmp);
+    free(tmp2);
+}
+
+/*
+ * Meson correlators of one point-source propagator (paper Sec. 4, Eq. 1):
+ *   C_Gamma(x) = - Tr( S^dag(x) g5 Gamma S(x) Gamma g5 ),
+ * summed over the sites of each time slice, C_Gamma(t) = sum_xvec C(xvec, t),
+ * with t counted from the source's time slice t0 (t_rel = (t - t0) mod Lt).
+ * S(x) is the 12 x 12 spin-colour matrix whose column (spin b, colour c) is
+ * the solution of M x = b for the point source of that spin and colour:
+ * props[12][V][4][3], column index 3 b + c. The trace runs over spin and
+ * colour. Gamma_n for n = 0..15 is the product g_x^n0 g_y^n1 g_z^n2 g_t^n3
+ * of the oracle's Dirac matrices (bits n0..n3 of n; n = 15 is g5).
+ * corr[n][t] (complex) for t = 0..Lt-1.
+ */
+void orc_meson(const cplx *props, const int L[4], int t0, cplx *corr)
+{
+    long V = volume4(L);
+    int Lt = L[3];
+    cplx G[16][4][4], A[16][4][4], B[16][4][4];
+    for (int n = 0; n < 16; ++n) {
+        cplx m[4][4], t[4][4];
+        memset(m, 0, sizeof m);
+        for (int i = 0; i < 4; ++i) m[i][i] = 1;
+        for (int mu = 0; mu < 4; ++mu)
+            if (n >> mu & 1) {
+                matmul4((const cplx(*)[4])m, (const cplx(*)[4])GAM[mu], t);
+                memcpy(m, t, sizeof m);
+            }
+        memcpy(G[n], m, sizeof m);
+        matmul4((const cplx(*)[4])GAM5, (const cplx(*)[4])G[n], A[n]);   /* g5 Gamma */
+        matmul4((const cplx(*)[4])G[n], (const cplx(*)[4])GAM5, B[n]);   /* Gamma g5 */
+    }
+    memset(corr, 0, sizeof(cplx) * 16 * Lt);
+    for (long s = 0; s < V; ++s) {
+        int c[4];
+        coords_of(L, s, c);
+        int tr = ((c[3] - t0) % Lt + Lt) % Lt;
+        /* S[i][j]: row i = (sink spin, colour), column j = (source spin, colour) */
+        cplx S[12][12];
+        for (int j = 0; j < 12; ++j)
+            for (int i = 0; i < 12; ++i) S[i][j] = props[((long)j * V + s) * 12 + i];
+        for (int n = 0; n < 16; ++n) {
+            /* SB = S (B (x) 1_colour); ASB = (A (x) 1_colour) SB;
+               Tr(S^dag ASB) = sum_{i,j} conj(S[j][i]) ASB[j][i] */
+            cplx SB[12][12], ASB[12][12];
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j) {
+                    cplx b = 0;
+                    for (int k = 0; k < 4; ++k) b += S[i][k * 3 + j % 3] * B[n][k][j / 3];
+                    SB[i][j] = b;
+                }
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j) {
+                    cplx a = 0;
+                    for (int k = 0; k < 4; ++k) a += A[n][i / 3][k] * SB[k * 3 + i % 3][j];
+                    ASB[i][j] = a;
+                }
+            cplx tr_ = 0;
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j) tr_ += conj(S[j][i]) * ASB[j][i];
+            corr[n * Lt + tr] += -tr_;
+        }
+    }
+}
+
 /* Mean plaquette: average over sites and the 6 planes of Re tr(U_mu nu)/3. */
 double orc_plaquette(const cplx *U, const int L[4])
 {

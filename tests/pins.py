@@ -360,6 +360,40 @@ def pin_tm_dense_and_adjoint(orc, dims=(2, 4, 2, 4), seed=41, kappa=0.12, mu=0.2
     assert rel(orc.mop_tm(U, psi, dims, kappa, 0.0), orc.mop(U, psi, dims, kappa)) < 1e-15
 
 
+def pin_tm_schur_block_elimination(orc, dims=(4, 2, 4, 6), kappa=0.13, mu=0.27):
+    """Block elimination of M(mu) on parity p: for psi supported on parity p and
+    x = psi + kappa A^-1 D_{1-p,p} psi (A = 1 + 2ik mu g5, inverted by LAPACK on
+    the dense site-diagonal matrix), M(mu) x equals S_p psi on parity p and
+    vanishes on parity 1-p; the adjoint is the conjugate transpose."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, 45)
+    G5 = _g5_dense(orc, V)
+    Ainv = np.linalg.inv(np.eye(12 * V) + 2j * kappa * mu * G5)
+    par = np.repeat(parity_index_sites(dims), 12)
+    for p in (0, 1):
+        psi = synth.gaussian_spinor(dims, 46 + p) * (parity_index_sites(dims) == p)[:, None, None]
+        d = orc.dslash_eo(U, psi, dims, 1 - p).reshape(-1)
+        x = psi.reshape(-1) + kappa * (Ainv @ d)
+        mx = orc.mop_tm(U, x.reshape(V, 4, 3), dims, kappa, mu).reshape(-1)
+        s = orc.schur_tm(U, psi, dims, kappa, mu, p).reshape(-1)
+        assert rel(mx[par == p], s[par == p]) < 1e-13
+        assert np.linalg.norm(mx[par != p]) < 1e-13 * np.linalg.norm(s)
+        assert not s[par != p].any()
+        phi = synth.gaussian_spinor(dims, 50 + p) * (parity_index_sites(dims) == p)[:, None, None]
+        lhs = np.vdot(phi, orc.schur_tm(U, psi, dims, kappa, mu, p))
+        rhs = np.vdot(orc.schur_tm(U, phi, dims, kappa, mu, p, dagger=True), psi)
+        assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    assert rel(orc.schur_tm(U, psi, dims, kappa, 0.0, 1), orc.schur(U, psi, dims, kappa, 1)) < 1e-15
+
+
+def parity_index_sites(dims):
+    """Parity (x+y+z+t) mod 2 of every site, canonical order."""
+    lx, ly, lz, lt = dims
+    t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
+                             indexing="ij")
+    return ((x + y + z + t) % 2).reshape(-1)
+
+
 def pin_tm_solve_lapack(orc, dims=(2, 4, 2, 4), kappa=0.12, mu=0.15):
     """CGNR on M(mu) reaches LAPACK's solution of the dense twisted system."""
     V = int(np.prod(dims))
@@ -372,6 +406,63 @@ def pin_tm_solve_lapack(orc, dims=(2, 4, 2, 4), kappa=0.12, mu=0.15):
     assert st["status"] == 0, st
     assert rel(x.reshape(-1), xs) <= np.linalg.cond(M) * 2e-11
     assert abs(orc.true_residual_tm(U, b, x, dims, kappa, mu) - st["true_res"]) < 1e-13
+
+
+def _random_props(dims, seed):
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((12, V, 4, 3)) + 1j * rng.standard_normal((12, V, 4, 3))
+
+
+def _site_matrix(props):
+    """S[x][i][j]: sink (spin, colour) i, source j = 3 b + c."""
+    V = props.shape[1]
+    return np.transpose(props.reshape(12, V, 12), (1, 2, 0))
+
+
+def pin_meson_pion_and_completeness(orc, dims=(2, 4, 2, 6)):
+    """Eq. 1 with Gamma = g5 is -sum |S|^2 per time slice; over the 16 Gammas,
+    sum_n Gamma_n^2 C_n = -4 sum_colours |Tr_spin S|^2 (the completeness of the
+    Dirac basis: sum_n Gamma_n X Gamma_n^-1 = 4 Tr(X) for 4 x 4 X, with
+    Gamma_n^-1 = Gamma_n^2 Gamma_n, Gamma_n^2 = +-1); t is counted from t0."""
+    g = gammas(orc)
+    V = int(np.prod(dims))
+    props = _random_props(dims, 61)
+    S = _site_matrix(props)
+    t_of = np.repeat(np.arange(dims[3]), V // dims[3])
+    for t0 in (0, 3):
+        C = orc.meson(props, dims, t0)
+        pion = np.zeros(dims[3])
+        comp = np.zeros(dims[3])
+        trs = np.einsum("xaiaj->xij", S.reshape(V, 4, 3, 4, 3))
+        for x in range(V):
+            tr = (t_of[x] - t0) % dims[3]
+            pion[tr] += np.sum(np.abs(S[x]) ** 2)
+            comp[tr] += np.sum(np.abs(trs[x]) ** 2)
+        assert rel(C[15], -pion) < 1e-13
+        sq = []
+        for n in range(16):
+            m = np.eye(4)
+            for mu in range(4):
+                if n >> mu & 1:
+                    m = m @ g[mu]
+            sq.append((m @ m)[0, 0].real)
+        assert rel(sum(sq[n] * C[n] for n in range(16)), -4 * comp) < 1e-13
+
+
+def pin_meson_gauge_invariance(orc, dims=(2, 2, 4, 4)):
+    """S(x) -> Omega(x) S(x) Omega(x0)^dag (colour rotations at sink and source)
+    leaves every C_Gamma(t) unchanged."""
+    V = int(np.prod(dims))
+    props = _random_props(dims, 62)
+    S = _site_matrix(props).reshape(V, 4, 3, 12)
+    om = synth.haar_su3(V, np.random.default_rng(63))
+    om0 = synth.haar_su3(1, np.random.default_rng(64))[0]
+    S2 = np.einsum("xab,xsbj->xsaj", om, S)                 # sink colour
+    S2 = S2.reshape(V, 12, 4, 3)
+    S2 = np.einsum("xisb,cb->xisc", S2, om0.conj())         # source colour
+    props2 = np.transpose(S2.reshape(V, 12, 12), (2, 0, 1)).reshape(12, V, 4, 3)
+    assert rel(orc.meson(props2, dims), orc.meson(props, dims)) < 1e-13
 
 
 def pin_plaquette(orc, dims=(4, 4, 2, 4)):
@@ -423,5 +514,7 @@ ALL_PINS = [
     pin_eo_split, pin_schur_dense, pin_sites, pin_solvers_lapack,
     pin_neumann, pin_free_field_solve, pin_eo_solve_odd_rows, pin_plaquette,
     pin_tm_free_field_spectrum, pin_tm_dense_and_adjoint, pin_tm_solve_lapack,
+    pin_tm_schur_block_elimination, pin_meson_pion_and_completeness,
+    pin_meson_gauge_invariance,
     pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]

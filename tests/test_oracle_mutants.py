@@ -70,6 +70,19 @@ MUTANTS = [
      "double tw = dagger ? -kappa * mu : kappa * mu;"),
     ("twist misses gamma5", "out[a][i] = w[a][i] + I * tw * g5psi[a][i];",
      "out[a][i] = w[a][i] + I * tw * raw[a][i];"),
+    ("twisted schur: A^-1 not inverted",
+     "(tmp[s * 12 + a * 3 + i] - I * t * g5v[a][i]) / (1.0 + t * t);",
+     "(tmp[s * 12 + a * 3 + i] + I * t * g5v[a][i]);"),
+    ("twisted schur: twist dropped on psi",
+     "? psi[k] + I * t * g5p[a][i] - kappa * kappa * tmp2[k]",
+     "? psi[k] - kappa * kappa * tmp2[k]"),
+    ("meson: source-side gamma5 on the wrong side",
+     "matmul4((const cplx(*)[4])G[n], (const cplx(*)[4])GAM5, B[n]);   /* Gamma g5 */",
+     "matmul4((const cplx(*)[4])GAM5, (const cplx(*)[4])G[n], B[n]);   /* Gamma g5 */"),
+    ("meson: S not conjugated", "tr_ += conj(S[j][i]) * ASB[j][i];",
+     "tr_ += S[j][i] * ASB[j][i];"),
+    ("meson: time not counted from t0", "int tr = ((c[3] - t0) % Lt + Lt) % Lt;",
+     "int tr = c[3];"),
     ("plaquette misses a conjugate",
      "acc += ab[i * 3 + k] * conj(e[j * 3 + k]);",
      "acc += ab[i * 3 + k] * e[j * 3 + k];"),
