@@ -4,25 +4,22 @@
 Workload (default): the 32^3 x 64 lattice (2,097,152 sites), links
 exp(i eps H) with eps = 0.35 (seed 0), kappa = 0.155, Gaussian source (seed 1),
 antiperiodic time. One step = pack the resident source, an even-odd
-preconditioned mixed-precision CG solve (FP32 Krylov iterations inside FP64
-defect correction) to ||b - M x|| / ||b|| <= 1e-10 recomputed in FP64, and
+preconditioned mixed-precision CG solve (FP32 Krylov iterations with FP64
+reliable updates) to ||b - M x|| / ||b|| <= 1e-10 recomputed in FP64, and
 unpack the solution.
 
-Printed: one JSON line. ``value`` is the whole-step throughput in algorithmic
-(compulsory) GB/s -- the library's per-kernel byte model summed over the step,
-divided by the step's wall time. ``roofline`` describes the dominant kernel
-(the FP32 even-odd hopping term) timed with HIP events on the stream it runs
-on; ``cpu_baseline`` times the FP64 CPU oracle's M apply on the same lattice
-(all host threads, and one), and the M apply and CGNR solve of the two small
-configurations.
-Also reported: solves/s, GFLOP/s, the plain FP64 solve it is compared with,
-the same solve with FP16-storage inner iterations, both mixed solves with
-12-real link storage, every Dslash variant's GB/s
-and GFLOP/s, the 12 point sources of a 24^3 x 48 propagator (batched operator
-and batched solve against single ones), an uneven batch of 64 small lattices
-(one call against 64 solves), and a served Poisson stream of mixed-size
-requests (saturation rate, p50/p99 latency at 0.5 and 0.8 of it, and the
-plain FP64 solver one request at a time on the same stream).
+Printed: stdout ends with one compact JSON line (the headline): ``value`` is
+the whole-step throughput in algorithmic (compulsory) GB/s -- the library's
+per-kernel byte model summed over the step, divided by the step's wall time;
+``roofline`` describes the dominant kernel (the FP32 even-odd hopping term)
+timed with HIP events on the stream it runs on, ``roofline_fp64_eo`` the
+paper's measured kernel (the FP64 even-odd hop); ``cpu_baseline`` times a
+bounded run of the FP64 CPU oracle's even-odd CGNR on the same system (all
+host threads); ``serving`` summarises the served streams. Everything else
+(every Dslash variant, the small configurations, the 12 point sources of a
+24^3 x 48 propagator and their meson correlators, the uneven batch of 64
+small lattices, the served Poisson streams by size, a twisted-mass solve, the
+autotuner's record) goes to stderr and to gpurun_out/bench_detail.json.
 """
 import argparse
 import json
@@ -184,6 +181,19 @@ def batch12(w, torch, synth, n_launch):
                         "iterations_max": max(x["iterations"] for x in st),
                         "true_res_max": max(x["true_res"] for x in st)}
         del work
+    # the meson correlators of Eq. 1 from the 12 propagator columns just solved
+    t0 = site // (dims[0] * dims[1] * dims[2])
+    mw = torch.empty(w.lib.wl_meson_workspace_bytes(w._dims(dims)), dtype=torch.uint8,
+                     device="cuda")
+    tmes = time_kernel(lambda: w.meson_correlators(X, dims, t0, work=mw, stream=s), n_launch,
+                       torch)
+    corr = w.meson_correlators(X, dims, t0, work=mw, stream=s).cpu()
+    out["meson_correlators"] = {
+        "us": tmes * 1e6, "GBs": 12 * V * 192 / tmes / 1e9,
+        "pion_C15": [float(v) for v in corr[15].real[:6]],
+        "note": "C_Gamma(t) of Eq. 1 for the 16 Gamma_n, t from the source slice; "
+                "GB/s counts the 12 FP64 propagator columns read once"}
+    del mw
     X1 = w.empty_spinor(dims)
     for f, name in ((w.EO, "sequential_f64_eo"), (w.EO | w.MIXED, "sequential_mixed_f32_eo"),
                     (w.EO | w.MIXED | w.F16S, "sequential_mixed_f16_eo")):
@@ -232,7 +242,8 @@ def uneven64(w, torch, synth, np):
                                                            stream=s), torch)
         assert code == 0 and max(x["true_res"] for x in st) <= 1e-10
         out["batched_" + name] = {"seconds": dt, "lattice_solves_per_s": 64 / dt,
-                                  "iterations_max": max(x["iterations"] for x in st)}
+                                  "iterations_max": max(x["iterations"] for x in st),
+                                  "algorithmic_GBs": sum(x["bytes"] for x in st) / dt / 1e9}
         wk = {}
         for p in probs:
             if p.dims not in wk:
@@ -443,21 +454,37 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots, merge):
 
     mixed = w.EO | w.MIXED | w.F16S
     out = {"hbm_budget_gb": budget_gb, "sizes": [[list(d), p] for d, p in SERVE_SIZES],
-           "kappa": [0.12, 0.155], "resident_fields": 8, "solver": "eo CG, FP16-storage inner, "
-           "FP64 reliable updates, tol 1e-10"}
+           "kappa": [0.12, 0.155], "resident_fields": 8,
+           "solver": "eo CG, FP16-storage inner, FP64 reliable updates, tol 1e-10",
+           "fp64_solver": "eo CG in FP64, one request at a time, tol 1e-10"}
+    # closed-loop saturation of each server (every request queued at once)
     sat = run(mixed, slots, None, max(100, n_req // 4), 40, 10, merge)
     S = sat["solves_per_s"]
-    log("serving: closed-loop saturation %.1f solves/s" % S)
     out["closed_loop"] = sat
     out["saturation_solves_per_s"] = S
+    sat64 = run(w.EO, 1, None, max(60, n_req // 8), 40, 5, 1)
+    S64 = sat64["solves_per_s"]
+    out["fp64_closed_loop"] = sat64
+    out["fp64_saturation_solves_per_s"] = S64
+    log("serving: closed-loop saturation %.1f solves/s (mixed, %d slots), %.1f (FP64, 1 slot)"
+        % (S, slots, S64))
+    # each server at 0.5 and 0.8 of its own saturation
     for frac, seed in ((0.5, 4), (0.8, 41)):
         r = run(mixed, slots, frac * S, n_req, seed, 20, merge)
         out["open_loop_%.1fS" % frac] = r
-        log("serving: %.1f S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
+        log("serving: mixed at %.1f S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
             % (frac, r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
-    r = run(w.EO, 1, 0.5 * S, n_req, 4, 20, 1)
-    out["fp64_one_at_a_time_0.5S"] = r
-    log("serving: FP64 one at a time at 0.5 S: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
+    n64 = max(100, n_req // 2)
+    for frac, seed in ((0.5, 4), (0.8, 41)):
+        r = run(w.EO, 1, frac * S64, n64, seed, 10, 1)
+        out["fp64_open_loop_%.1fS64" % frac] = r
+        log("serving: FP64 at %.1f S64: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
+            % (frac, r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
+    # the mixed server on the very stream the FP64 server got at 0.5 S64: one
+    # offered rate below both capacities, so both latencies are service times
+    r = run(mixed, slots, 0.5 * S64, n64, 4, 10, merge)
+    out["mixed_at_0.5S64"] = r
+    log("serving: mixed at 0.5 S64: %.1f solves/s, p50 %.1f ms, p99 %.1f ms"
         % (r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
     del fields, sources, xpool
     torch.cuda.empty_cache()
@@ -581,6 +608,24 @@ def main():
             del wk
         del G12, X12
 
+    # the twisted-mass operator of the paper's action, mu = 0.01, with the
+    # step's solver (mixed-precision eo-CG); the twist bounds sigma_min(M)
+    # from below by 2 kappa mu, so it converges in fewer iterations
+    tm = None
+    if not args.no_fp64_compare:
+        mu = 0.01
+        wk = torch.empty(w.workspace_bytes(dims, flags), dtype=torch.uint8, device="cuda")
+        Xt = w.empty_spinor(dims)
+        w.solve_cg_tm(G64, B, Xt, dims, kappa, mu, tol=1e-10, maxiter=20000, flags=flags,
+                      work=wk, stream=s)
+        stt, dt = timed(lambda: w.solve_cg_tm(G64, B, Xt, dims, kappa, mu, tol=1e-10,
+                                              maxiter=20000, flags=flags, work=wk, stream=s),
+                        torch)
+        assert stt["status"] == 0 and stt["true_res"] <= 1e-10, stt
+        tm = {"mu": mu, "seconds": dt, "iterations": stt["iterations"],
+              "true_res": stt["true_res"], "algorithmic_GBs": stt["bytes"] / dt / 1e9}
+        del wk, Xt
+
     # Dslash variants, each timed over a run of launches (HIP events)
     variants = {}
     n = args.kernel_launches
@@ -632,6 +677,17 @@ def main():
                 "bytes_per_launch": per_launch, "avg_us": variants[dom]["us"],
                 "frac_of_copy": ach / best_copy}
 
+    # the paper's measured kernel (Sec. 3, Fig. 5): the FP64 even-odd hop
+    dom64 = "Deo_f64_%s" % ("12" if args.link12 else "18")
+    lb64 = 16 * (6 if args.link12 else 9)
+    per64 = Vh * (2 * 192 + 8 * lb64)
+    roofline64 = {"bound": "hbm", "achieved": variants[dom64]["GBs"], "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": variants[dom64]["GBs"] / HBM_PEAK_GBS,
+                  "kernel": "wl::hop_kernel<double, %d, false, false, 0, 1, true> "
+                            "(even-odd hop, FP64)" % (6 if args.link12 else 9),
+                  "bytes_per_launch": per64, "avg_us": variants[dom64]["us"],
+                  "gflops": variants[dom64]["GFLOPs"]}
+
     small = None if args.no_small else small_configs(w, torch, synth, args.kernel_launches)
 
     batch = uneven = None
@@ -662,11 +718,26 @@ def main():
         for _ in range(nrep):
             oracle.mop(U, b, dims, kappa)
         dt = (time.perf_counter() - t) / nrep
-        cpu = {"value": 960.0 * V / dt / 1e9, "unit": "GB/s", "cores": oracle.max_threads(),
-               "kind": "oracle",
-               "sample": "%d FP64 M applies of the oracle on the %s lattice; %.2f s each, "
-                         "%.2f GFLOP/s at 1368 flop/site; GB/s counts 960 B/site like the "
-                         "GPU M" % (nrep, args.workload, dt, 1368.0 * V / dt / 1e9),
+        # the step's own method on the host: a bounded number of the oracle's
+        # FP64 even-odd CGNR iterations on the same system (the tolerance is
+        # out of reach, so exactly `its` iterations run), counted with the
+        # library's byte model of an FP64 eo-CG iteration (2 Schur applies of
+        # 2 half hops, 1536 B per output site each, plus the xpay read, and 9
+        # vector passes): Vh * (2 * (2 * 1536 + 192) + 9 * 192) bytes
+        its = 30
+        t = time.perf_counter()
+        _, ost = oracle.cgnr_eo(U, b, dims, kappa, tol=1e-30, maxiter=its)
+        dt_cg = time.perf_counter() - t
+        iter_bytes = Vh * (2 * (2 * 1536 + 192) + 9 * 192)
+        cpu = {"value": iter_bytes * ost["iterations"] / dt_cg / 1e9, "unit": "GB/s",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "%d iterations of the oracle's FP64 even-odd CGNR on the %s "
+                         "lattice (%.1f s; %.0f MB per iteration in the GPU solver's byte "
+                         "model); the oracle's M apply on the same field: %.2f s, %.2f "
+                         "GFLOP/s at 1368 flop/site" % (ost["iterations"], args.workload, dt_cg,
+                                                         iter_bytes / 1e6, dt,
+                                                         1368.0 * V / dt / 1e9),
+               "seconds_per_iteration": dt_cg / max(ost["iterations"], 1),
                "seconds_per_apply": dt}
         # one host thread on the same apply; the M apply of the 4^4 and
         # 16^3 x 32 configurations (median of 10 / 3) and their CGNR solves to
@@ -695,17 +766,52 @@ def main():
                                         "cgnr_iterations": ost["iterations"],
                                         "cgnr_true_res": ost["true_res"]})
         cpu["small_configs"] = small_cpu
-        cpu["not_timed"] = ("the oracle's solve at %s (CGNR, about 500 iterations of two "
-                            "full-lattice applies: minutes of CPU)" % args.workload)
 
+    detail = {
+        "fp64_solve": fp64,
+        "mixed_f16_solve": f16,
+        "link12_solves": link12_solves,
+        "twisted_mass_solve": tm,
+        "dslash_variants": variants,
+        "device_copy": copy,
+        "roofline": roofline,
+        "roofline_fp64_eo": roofline64,
+        "cpu_baseline": cpu,
+        "small_configs": small,
+        "batch12_point_sources": batch,
+        "uneven64_lattices": uneven,
+        "serving": serve,
+    }
+    # the details go to stderr and to a file; stdout ends with one compact line
+    log("detail: " + json.dumps(detail))
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as f:
+        json.dump(detail, f, indent=1)
+
+    def pick(d, *keys):
+        return None if d is None else {k: d[k] for k in keys if k in d}
+
+    serve_sum = None
+    if serve:
+        serve_sum = {
+            "mixed_saturation": serve["saturation_solves_per_s"],
+            "fp64_saturation": serve["fp64_saturation_solves_per_s"]}
+        for key, name in (("open_loop_0.5S", "mixed_0.5S"), ("open_loop_0.8S", "mixed_0.8S"),
+                          ("mixed_at_0.5S64", "mixed_at_0.5S64"),
+                          ("fp64_open_loop_0.5S64", "fp64_0.5S64"),
+                          ("fp64_open_loop_0.8S64", "fp64_0.8S64")):
+            r = serve[key]
+            serve_sum[name] = [round(r["offered_rate"], 1), round(r["solves_per_s"], 1),
+                               round(r["p50_ms"], 1), round(r["p99_ms"], 1)]
+        serve_sum["fields"] = "offered req/s, solves/s, p50 ms, p99 ms"
     out = {
         "metric": "Dslash GB/s (% HBM peak) & GFLOP/s; solves/s + p99 latency, mixed vs FP64",
-        "value": value,
+        "value": round(value, 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": round(ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -715,25 +821,29 @@ def main():
                    "lattice": list(dims), "kappa": kappa, "links": "exp(i*%.2f*H), seed 0" % eps,
                    "link_storage": "12-real" if args.link12 else "18-real",
                    "tol": 1e-10, "parallelism": "single GPU"},
-        "pct_hbm_peak": 100.0 * value / HBM_PEAK_GBS,
-        "solves_per_s": 1e3 / ms,
-        "gflops": step_flops / (ms / 1e3) / 1e9,
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "gflops": round(step_flops / (ms / 1e3) / 1e9, 1),
+        "solves_per_s": round(1e3 / ms, 3),
         "iterations": int(np.mean([st["iterations"] for st in stats])),
-        "outer_corrections": int(np.mean([st["restarts"] for st in stats])),
         "true_res": max(st["true_res"] for st in stats),
-        "fp64_solve": fp64,
-        "mixed_f16_solve": f16,
-        "link12_solves": link12_solves,
-        "dslash_variants": variants,
-        "device_copy": copy,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "small_configs": small,
-        "batch12_point_sources": batch,
-        "uneven64_lattices": uneven,
-        "serving": serve,
+        "fp64_solve_s": None if fp64 is None else round(fp64["seconds"], 4),
+        "mixed_vs_fp64": None if fp64 is None else round(fp64["mixed_speedup"], 3),
+        "f16_inner_solve_s": None if f16 is None else round(f16["seconds"], 4),
+        "roofline": pick(roofline, "bound", "achieved", "peak", "unit", "frac", "traffic",
+                         "kernel", "bytes_per_launch", "avg_us"),
+        "roofline_fp64_eo": pick(roofline64, "bound", "achieved", "peak", "unit", "frac",
+                                 "kernel", "bytes_per_launch", "avg_us"),
+        "cpu_baseline": pick(cpu, "value", "unit", "cores", "kind", "sample",
+                             "seconds_per_iteration", "seconds_per_apply",
+                             "seconds_per_apply_1_core"),
+        "serving": serve_sum,
+        "detail_file": "gpurun_out/bench_detail.json",
     }
-    print(json.dumps(out))
+    for k in ("roofline", "roofline_fp64_eo"):
+        if out[k]:
+            for f in ("achieved", "frac", "avg_us"):
+                out[k][f] = round(out[k][f], 4)
+    print(json.dumps(out), flush=True)
     return 0
 
 

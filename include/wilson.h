@@ -93,7 +93,10 @@ extern "C" {
  * WL_TUNE_FILE=path     keep the autotuner's choices in this file
  * WL_TUNE_FORCE=n,c,g   impose one launch shape on every hop launch (testing)
  * WL_DELTA_F32=d        reliable-update threshold of FP32-inner mixed CG
- *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.2)
+ *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.2);
+ *                       WL_DELTA_BI_F32 / WL_DELTA_BI_F16 for mixed BiCGStab
+ *                       (defaults 0.1 / 0.3)
+ * WL_TRACE=1            one line per solver pass on stderr
  * None of these changes a result's bits except the WL_DELTA_* thresholds.  */
 
 /* ---- status codes -------------------------------------------------------- */
@@ -114,6 +117,11 @@ typedef struct {
     double seconds;           /* wall time of the solve                       */
     double flops;             /* model flops (1320/site per D_W)              */
     double bytes;             /* algorithmic bytes moved by all kernels       */
+    int32_t fp64_iterations;  /* Krylov iterations run in FP64: all of them
+                                 without WL_MIXED; with it, those of a mixed
+                                 BiCGStab that continued in FP64 after its
+                                 low-precision sequence stalled (0 for CG)    */
+    int32_t reserved;         /* 0                                            */
 } wl_solve_stats;
 
 /* Library version string and the thread-local message of the last error. */
@@ -155,16 +163,40 @@ int wilson_dslash(const void *gauge, const void *in, void *out,
 /* Even-odd operator (paper Sec. 3: the even-odd preconditioned dslash).
  *   WL_HOP:   out (half field, parity out_parity)
  *               = D_{p,1-p} in   (in: half field of parity 1 - out_parity)
- *   default:  out = Mhat_p in = in - kappa^2 D_{p,1-p} D_{1-p,p} in,
- *             in and out both half fields of parity p = out_parity; the
- *             intermediate half field is taken from the stream-ordered
- *             allocator of `stream`.
+ *   default:  the Schur complement Mhat_p = 1 - kappa^2 D_{p,1-p} D_{1-p,p}
+ *             on p = out_parity. `in` is a half field of parity p and `out`
+ *             a FULL field (wl_spinor_bytes(dims, flags, 2) bytes): its
+ *             parity-p block receives Mhat_p in, and its parity-(1-p) block
+ *             is overwritten with the intermediate D_{1-p,p} in. The library
+ *             allocates nothing; `in` must not overlap either block of out.
  *   WL_DAG:   adjoint of the above.
  * Asynchronous on `stream`. */
 int wilson_dslash_eo(const void *gauge, const void *in, void *out,
                      const int32_t dims[4], double kappa,
                      const double phases[8], int32_t out_parity,
                      uint32_t flags, void *stream);
+
+/* Twisted-mass Wilson fermions (paper Sec. 3: the group's N_f = 2 twisted-mass
+ * Wilson action; one flavour, the other is mu -> -mu):
+ *   M(mu) = 1 + 2 i kappa mu gamma_5 - kappa D_W,
+ *   M(mu)^dag = 1 - 2 i kappa mu gamma_5 - kappa D_W^dag = gamma_5 M(-mu) gamma_5.
+ * wilson_dslash_tm: the modes of wilson_dslash for M(mu) (WL_HOP returns D_W,
+ * independent of mu). wilson_dslash_eo_tm: WL_HOP as wilson_dslash_eo; the
+ * default mode is the Schur complement on p = out_parity of the diagonal
+ * A = 1 + 2 i kappa mu gamma_5,
+ *   S_p = A - kappa^2 D_{p,1-p} A^-1 D_{1-p,p},
+ *   A^-1 = (1 - 2 i kappa mu gamma_5) / (1 + 4 kappa^2 mu^2),
+ * with `out` a full field as for wilson_dslash_eo (its parity-(1-p) block
+ * receives A^-1 D_{1-p,p} in); WL_DAG gives S_p^dag. mu = 0 gives exactly the
+ * Wilson calls. Arguments, layouts and errors otherwise as for the Wilson
+ * entry points; WL_EINVAL when mu is not finite. */
+int wilson_dslash_tm(const void *gauge, const void *in, void *out,
+                     const int32_t dims[4], double kappa, double mu,
+                     const double phases[8], uint32_t flags, void *stream);
+int wilson_dslash_eo_tm(const void *gauge, const void *in, void *out,
+                        const int32_t dims[4], double kappa, double mu,
+                        const double phases[8], int32_t out_parity,
+                        uint32_t flags, void *stream);
 
 /* Scratch bytes the solvers need for these dims and flags (nrhs = 1). */
 size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
@@ -178,11 +210,16 @@ size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
  * reconstruct x_o = b_o + kappa D_oe x_e. With WL_MIXED the Krylov iterations
  * run in low precision -- FP32 (WL_F32 or no precision bits) or FP16 storage
  * with FP32 arithmetic (WL_F16S) -- on a copy of the links made at the start
- * of the solve: CG keeps one Krylov sequence and refreshes the FP64 solution
- * and residual whenever the low-precision residual has dropped by 10x (5x for
- * FP16) ("reliable updates"); BiCGStab restarts its low-precision solve of
- * M e = r from each FP64 residual (defect correction). FP64 is used only for
- * the solution, the residuals, and the global reductions.
+ * of the solve, as one Krylov sequence with reliable updates: whenever the
+ * low-precision residual norm has dropped by a factor delta since the last
+ * update, the correction is added to the FP64 solution and the residual is
+ * recomputed in FP64 and replaces the low-precision one. delta is 3e-3 (FP32
+ * inner) or 0.2 (FP16) for CG, also updating when the residual has not halved
+ * in 300 iterations, and 0.1 / 0.3 for BiCGStab (environment WL_DELTA_F32,
+ * WL_DELTA_F16, WL_DELTA_BI_F32, WL_DELTA_BI_F16). A mixed BiCGStab whose
+ * low-precision pass makes no progress continues in FP64 from its best
+ * iterate (stats->fp64_iterations). FP64 is used for the solution, the
+ * residuals, and the global reductions.
  * `gauge` is the packed FP64 gauge field (link format per flags); `b` and `x`
  * are packed FP64 full spinors; x is the initial guess with WL_X0, otherwise
  * it is overwritten from zero. `work` is device scratch of at least
@@ -196,6 +233,22 @@ int solve_bicgstab(const void *gauge, const void *b, void *x,
                    const int32_t dims[4], double kappa, const double phases[8],
                    double tol, int32_t maxiter, uint32_t flags, void *work,
                    size_t work_bytes, wl_solve_stats *stats, void *stream);
+
+/* Solve M(mu) x = b for the twisted-mass operator above; everything else as
+ * for solve_cg / solve_bicgstab (same flags, workspace size, statuses). With
+ * WL_EO the Krylov iterations run on the Schur system
+ * S_e x_e = b_e + kappa D_eo A^-1 b_o and x_o = A^-1 (b_o + kappa D_oe x_e);
+ * acceptance is on ||b - M(mu) x|| / ||b|| in FP64. mu = 0 gives exactly
+ * solve_cg / solve_bicgstab. */
+int solve_cg_tm(const void *gauge, const void *b, void *x, const int32_t dims[4],
+                double kappa, double mu, const double phases[8], double tol,
+                int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                wl_solve_stats *stats, void *stream);
+int solve_bicgstab_tm(const void *gauge, const void *b, void *x,
+                      const int32_t dims[4], double kappa, double mu,
+                      const double phases[8], double tol, int32_t maxiter,
+                      uint32_t flags, void *work, size_t work_bytes,
+                      wl_solve_stats *stats, void *stream);
 
 /* Batched operator: `in` and `out` each hold nrhs packed full spinors one
  * after another (stride wl_spinor_bytes(dims, flags, 2)); the modes are those
@@ -247,6 +300,23 @@ size_t wl_problems_workspace_bytes(const wl_problem *p, int32_t n, uint32_t flag
 int solve_cg_problems(const wl_problem *p, int32_t n, const double phases[8], double tol,
                       int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream);
+
+/* Meson correlators of one point-source propagator (paper Sec. 4, Eq. 1):
+ *   C_Gamma(t) = - sum_xvec Tr( S^dag(x) g5 Gamma S(x) Gamma g5 ),  x = (xvec, t),
+ * where the columns of the 12 x 12 spin-colour matrix S(x) are the 12
+ * solutions of M x = b for the point sources of spin b and colour c at one
+ * site (e.g. the result of solve_cg_batch on those sources): `props` holds
+ * the 12 packed FP64 full spinors one after another (stride
+ * wl_spinor_bytes(dims, WL_F64, 2)), field 3 b + c. The trace runs over spin
+ * and colour, the 16 Gamma_n = g_x^n0 g_y^n1 g_z^n2 g_t^n3 (bits n0..n3 of
+ * n; Gamma_15 = g5, Gamma_0 = 1) are those of the chiral basis, and t is
+ * counted from the source's time slice t0 (0 <= t0 < Lt). `corr` (device)
+ * receives double[16][Lt][2] (real, imaginary parts). Sums run in a fixed
+ * order (bitwise reproducible). `work` is device scratch of
+ * wl_meson_workspace_bytes(dims) bytes. Asynchronous on `stream`. */
+size_t wl_meson_workspace_bytes(const int32_t dims[4]);
+int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0,
+                         double *corr, void *work, size_t work_bytes, void *stream);
 
 /* Streaming device-to-device copy of `bytes` bytes (both pointers 16-byte
  * aligned, bytes a multiple of 16; the buffers must not overlap), loads then

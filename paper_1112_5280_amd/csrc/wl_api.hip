@@ -162,6 +162,12 @@ int wl_unpack_spinor(const void *packed, void *canon, const int32_t dims[4], uin
 
 int wilson_dslash(const void *gauge, const void *in, void *out, const int32_t dims[4],
                   double kappa, const double phases[8], uint32_t flags, void *stream) {
+    return wilson_dslash_tm(gauge, in, out, dims, kappa, 0.0, phases, flags, stream);
+}
+
+int wilson_dslash_tm(const void *gauge, const void *in, void *out, const int32_t dims[4],
+                     double kappa, double mu, const double phases[8], uint32_t flags,
+                     void *stream) {
     Geom g;
     Phases ph;
     std::string why;
@@ -172,6 +178,7 @@ int wilson_dslash(const void *gauge, const void *in, void *out, const int32_t di
     if (!gauge || !in || !out) return fail(WL_EINVAL, "NULL buffer");
     if (in == out) return fail(WL_EINVAL, "in and out alias");
     if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (!std::isfinite(mu)) return fail(WL_EINVAL, "mu is not finite");
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
     const size_t blk = spinor_block_bytes(g, prec);
     HopCall c{};
@@ -180,16 +187,19 @@ int wilson_dslash(const void *gauge, const void *in, void *out, const int32_t di
     c.in[1] = static_cast<const char *>(in) + blk;
     c.out[0] = out;
     c.out[1] = static_cast<char *>(out) + blk;
+    c.dag = flags & WL_DAG;
     if (!(flags & WL_HOP)) {
         c.xs[0] = c.in[0];
         c.xs[1] = c.in[1];
         c.c = -kappa;
+        // twisted mass: (1 + 2 i kappa mu g5) in - kappa D in; adjoint -mu
+        const double tw = 2.0 * kappa * mu;
+        if (tw != 0.0) c.tx = c.dag ? -tw : tw;
     } else {
         c.c = 1.0;
     }
     c.first_par = 0;
     c.npar = 2;
-    c.dag = flags & WL_DAG;
     const hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c,
                                     static_cast<hipStream_t>(stream));
     return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash");
@@ -198,6 +208,13 @@ int wilson_dslash(const void *gauge, const void *in, void *out, const int32_t di
 int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t dims[4],
                      double kappa, const double phases[8], int32_t out_parity, uint32_t flags,
                      void *stream) {
+    return wilson_dslash_eo_tm(gauge, in, out, dims, kappa, 0.0, phases, out_parity, flags,
+                               stream);
+}
+
+int wilson_dslash_eo_tm(const void *gauge, const void *in, void *out, const int32_t dims[4],
+                        double kappa, double mu, const double phases[8], int32_t out_parity,
+                        uint32_t flags, void *stream) {
     Geom g;
     Phases ph;
     std::string why;
@@ -209,6 +226,8 @@ int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t
     if (in == out) return fail(WL_EINVAL, "in and out alias");
     if (out_parity != 0 && out_parity != 1) return fail(WL_EINVAL, "out_parity must be 0 or 1");
     if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
+    if (!std::isfinite(mu)) return fail(WL_EINVAL, "mu is not finite");
+    const double tw = 2.0 * kappa * mu;   // twist of A = 1 + i tw g5
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int p = out_parity, q = 1 - out_parity;
@@ -225,10 +244,17 @@ int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t
         const hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c, s);
         return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_eo");
     }
-    // Schur complement: tmp_q = D_{q,p} in; out = in - kappa^2 D_{p,q} tmp_q
-    void *tmp = nullptr;
-    hipError_t e = hipMallocAsync(&tmp, spinor_block_bytes(g, prec), s);
-    if (e != hipSuccess) return hip_fail(e, "wilson_dslash_eo: scratch allocation");
+    // Schur complement: tmp_q = D_{q,p} in; out_p = in - kappa^2 D_{p,q} tmp_q.
+    // `out` is a full field here: its parity-q block holds the intermediate,
+    // so the call needs no scratch of its own.
+    const size_t blk = spinor_block_bytes(g, prec);
+    void *outp = static_cast<char *>(out) + size_t(p) * blk;
+    void *tmp = static_cast<char *>(out) + size_t(q) * blk;
+    {
+        const char *ib = static_cast<const char *>(in), *ob = static_cast<const char *>(out);
+        if (ib < ob + 2 * blk && ob < ib + blk)
+            return fail(WL_EINVAL, "in overlaps the two parity blocks of out");
+    }
     HopCall c1{};
     c1.gauge = gauge;
     c1.in[p] = in;
@@ -237,23 +263,25 @@ int wilson_dslash_eo(const void *gauge, const void *in, void *out, const int32_t
     c1.npar = 1;
     c1.c = 1.0;
     c1.dag = dag;
-    e = launch_hop(g, prec, flags & WL_LINK12, ph, c1, s);
+    if (tw != 0.0) {   // tmp = A^-1 D in  (adjoint: A^-dag D^dag in)
+        c1.c = 1.0 / (1.0 + tw * tw);
+        c1.ta = dag ? tw : -tw;
+    }
+    hipError_t e = launch_hop(g, prec, flags & WL_LINK12, ph, c1, s);
     if (e == hipSuccess) {
         HopCall c2{};
         c2.gauge = gauge;
         c2.in[q] = tmp;
         c2.xs[p] = in;
-        c2.out[p] = out;
+        c2.out[p] = outp;
         c2.first_par = p;
         c2.npar = 1;
         c2.c = -kappa * kappa;
         c2.dag = dag;
+        if (tw != 0.0) c2.tx = dag ? -tw : tw;   // A in - kappa^2 D tmp
         e = launch_hop(g, prec, flags & WL_LINK12, ph, c2, s);
     }
-    const hipError_t ef = hipFreeAsync(tmp, s);
-    if (e != hipSuccess) return hip_fail(e, "wilson_dslash_eo");
-    if (ef != hipSuccess) return hip_fail(ef, "wilson_dslash_eo: scratch release");
-    return WL_OK;
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_eo");
 }
 
 size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs) {
@@ -397,8 +425,10 @@ int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
 static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
                         const int32_t dims[4], double kappa, const double phases[8], double tol,
                         int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
-                        wl_solve_stats *stats, void *stream) {
+                        wl_solve_stats *stats, void *stream, double mu = 0.0) {
     SolveIn in{};
+    if (!std::isfinite(mu)) return fail(WL_EINVAL, "mu is not finite");
+    in.mu = mu;
     std::string why;
     if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
         return fail(WL_EINVAL, why);
@@ -446,12 +476,49 @@ int solve_cg(const void *gauge, const void *b, void *x, const int32_t dims[4], d
                         work_bytes, stats, stream);
 }
 
+int solve_cg_tm(const void *gauge, const void *b, void *x, const int32_t dims[4], double kappa,
+                double mu, const double phases[8], double tol, int32_t maxiter, uint32_t flags,
+                void *work, size_t work_bytes, wl_solve_stats *stats, void *stream) {
+    return solve_common(false, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
+                        work_bytes, stats, stream, mu);
+}
+
+int solve_bicgstab_tm(const void *gauge, const void *b, void *x, const int32_t dims[4],
+                      double kappa, double mu, const double phases[8], double tol,
+                      int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
+                      wl_solve_stats *stats, void *stream) {
+    return solve_common(true, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
+                        work_bytes, stats, stream, mu);
+}
+
 int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims[4],
                    double kappa, const double phases[8], double tol, int32_t maxiter,
                    uint32_t flags, void *work, size_t work_bytes, wl_solve_stats *stats,
                    void *stream) {
     return solve_common(true, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
                         work_bytes, stats, stream);
+}
+
+size_t wl_meson_workspace_bytes(const int32_t dims[4]) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why)) return 0;
+    return meson_workspace_bytes(g);
+}
+
+int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0, double *corr,
+                         void *work, size_t work_bytes, void *stream) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why)) return fail(WL_EINVAL, why);
+    if (!props || !corr || !work) return fail(WL_EINVAL, "NULL buffer");
+    if (t0 < 0 || t0 >= dims[3]) return fail(WL_EINVAL, "t0 must be a time slice of the lattice");
+    const size_t need = meson_workspace_bytes(g);
+    if (work_bytes < need)
+        return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                       " bytes, got " + std::to_string(work_bytes));
+    const hipError_t e = launch_meson(g, props, t0, corr, work, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_meson_correlators");
 }
 
 int wl_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {

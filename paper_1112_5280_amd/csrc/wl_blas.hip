@@ -21,7 +21,7 @@ struct BlasArgs {
     size_t fstride;       // bytes between the fields of consecutive RHS
     size_t blk;           // bytes between parity blocks of one field
     char *v[6];
-    double a;
+    double a, b;
     Scalars *sc;          // RHS r reads sc[r]
     const int *skip;
     Reduce red;
@@ -46,10 +46,13 @@ template <> struct OpSums<kOpCgXR> { static constexpr int value = 1; };
 template <> struct OpSums<kOpBiXR> { static constexpr int value = 3; };
 template <> struct OpSums<kOpCopyNorm2> { static constexpr int value = 1; };
 template <> struct OpSums<kOpCopy2Norm2> { static constexpr int value = 1; };
+template <> struct OpSums<kOpNormDot> { static constexpr int value = 3; };
+
+static int OpSumsOf(int op) { return (op == kOpBiXR || op == kOpNormDot) ? 3 : 1; }
 
 static bool op_reduces(int op) {
     return op == kOpNorm2 || op == kOpXmy || op == kOpCgXR || op == kOpBiXR ||
-           op == kOpCopyNorm2 || op == kOpCopy2Norm2;
+           op == kOpCopyNorm2 || op == kOpCopy2Norm2 || op == kOpNormDot;
 }
 
 template <typename ST, int OP>
@@ -80,6 +83,43 @@ __global__ void __launch_bounds__(kBlock) blas_kernel(BlasArgs a) {
         } else if constexpr (OP == kOpNorm2) {
             load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
             sums[0] = norm2(x);
+        } else if constexpr (OP == kOpRandom) {     // counter-based pseudo-random field
+            // SplitMix64 finaliser of (seed, parity, site, component): the
+            // value of an entry does not depend on the launch shape
+            const uint64_t base = (uint64_t(a.a) << 40) ^ (uint64_t(par) << 39) ^
+                                  (uint64_t(i) * 24u);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                float u[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    uint64_t z = base + uint64_t(2 * k + c) + 0x9e3779b97f4a7c15ull;
+                    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+                    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+                    z ^= z >> 31;
+                    u[c] = float(int64_t(z >> 11) - (int64_t(1) << 52)) * float(1.0 / 4503599627370496.0);
+                }
+                y[k] = {R(u[0]), R(u[1])};
+            }
+            store_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, y);
+        } else if constexpr (OP == kOpTwist) {      // y = a (1 + i b g5) x
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            const R s = R(a.a);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const R t = R(k < 6 ? a.b : -a.b);
+                y[k] = s * (x[k] + t * ci(x[k]));
+            }
+            store_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
+        } else if constexpr (OP == kOpNormDot) {    // ||y||^2, <x, y>
+            load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
+            load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
+            sums[0] = norm2(y);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                sums[1] += double(x[k].re) * double(y[k].re) + double(x[k].im) * double(y[k].im);
+                sums[2] += double(x[k].re) * double(y[k].im) - double(x[k].im) * double(y[k].re);
+            }
         } else if constexpr (OP == kOpXmy) {        // y = x - y
             load_spinor<ST>(blk_ptr(a, 0, par, fo), S, i, x);
             load_spinor<ST>(blk_ptr(a, 1, par, fo), S, i, y);
@@ -246,6 +286,9 @@ static hipError_t blas_storage(const BlasArgs &a, int op, hipStream_t s) {
         WL_CASE(kOpAxpy)
         WL_CASE(kOpCopyNorm2)
         WL_CASE(kOpCopy2Norm2)
+        WL_CASE(kOpNormDot)
+        WL_CASE(kOpRandom)
+        WL_CASE(kOpTwist)
     default: return hipErrorInvalidValue;
     }
 #undef WL_CASE
@@ -266,6 +309,7 @@ hipError_t launch_blas(const Geom &g, int prec, const BlasCall &call, hipStream_
     a.blk = spinor_block_bytes(g, prec);
     for (int k = 0; k < 6; ++k) a.v[k] = static_cast<char *>(call.v[k]);
     a.a = call.a;
+    a.b = call.b;
     a.sc = call.sc;
     a.skip = call.skip;
     if (call.red) a.red = *call.red;
@@ -273,7 +317,7 @@ hipError_t launch_blas(const Geom &g, int prec, const BlasCall &call, hipStream_
     const hipError_t e =
         with_storage(prec, [&](auto tag) { return blas_storage<decltype(tag)>(a, call.op, s); });
     if (e != hipSuccess || !op_reduces(call.op)) return e;
-    return launch_finish(a.red, call.op == kOpBiXR ? 3 : 1, a.nb_rhs, a.nrhs, a.skip, s);
+    return launch_finish(a.red, OpSumsOf(call.op), a.nb_rhs, a.nrhs, a.skip, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -50,12 +50,12 @@ void tune_store_locked(const std::string &key, const TuneEntry &e) {
 }  // namespace
 
 std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, int red,
-                     int nrhs, int npar) {
-    char k[160];
+                     int nrhs, int npar, bool own_gauges) {
+    char k[176];
     std::snprintf(k, sizeof k, "hop prec=%d link=%d dag=%d xpay=%d red=%d nrhs=%d npar=%d "
-                               "L=%dx%dx%dx%d",
-                  prec, link12 ? 12 : 18, int(dag), int(xpay), red, nrhs, npar, g.L[0], g.L[1],
-                  g.L[2], g.L[3]);
+                               "gauges=%s L=%dx%dx%dx%d",
+                  prec, link12 ? 12 : 18, int(dag), int(xpay), red, nrhs, npar,
+                  own_gauges ? "per-rhs" : "shared", g.L[0], g.L[1], g.L[2], g.L[3]);
     return k;
 }
 

@@ -104,6 +104,9 @@ struct HopArgs {
     const Scalars *ksc;        // per-RHS kappa (or null: `c` shared)
     double cmul;
     int cpow;
+    // twisted mass: out = sx (1 + i tx g5) xs + c (1 + i ta g5) acc when twist
+    bool twist;
+    R tx, ta, sx;
 };
 
 template <int MU, int S, typename R>
@@ -418,10 +421,27 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
             if (NR > 1 && !on[r]) continue;
             cpx<R> o[12];
             cpx<R> xv[12];
+            if (a.twist) {
+                // diagonal twist (1 + i t g5) on the hopping term; g5 =
+                // diag(1, 1, -1, -1) on the spins of the chiral basis
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const R t = k < 6 ? a.ta : -a.ta;
+                    acc[r][k] = acc[r][k] + t * ci(acc[r][k]);
+                }
+            }
             if constexpr (XPAY) {
                 load_spinor<ST, NTL>(static_cast<const char *>(a.xs[p]) + fo[r], g.S, i, xv);
+                if (a.twist) {
 #pragma unroll
-                for (int k = 0; k < 12; ++k) o[k] = xv[k] + c[r] * acc[r][k];
+                    for (int k = 0; k < 12; ++k) {
+                        const R t = k < 6 ? a.tx : -a.tx;
+                        o[k] = a.sx * (xv[k] + t * ci(xv[k])) + c[r] * acc[r][k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) o[k] = xv[k] + c[r] * acc[r][k];
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) o[k] = c[r] * acc[r][k];
@@ -498,6 +518,9 @@ struct Shape {
 
 template <typename ST, int NCL, bool DAG, bool XPAY, int RED>
 static hipError_t launch_nr(const HopArgs<Real<ST>> &a, Shape sh, hipStream_t s) {
+    // with a per-RHS gauge table a thread's links are those of its first RHS,
+    // so it may own only that one
+    if (a.gtab) sh.nr = 1;
     if constexpr (blocked_ok<ST, RED>()) {
         switch (sh.nr) {
         case 2: return launch_kernel<ST, NCL, DAG, XPAY, RED, 2>(a, sh.chunk, sh.tg, s);
@@ -529,7 +552,7 @@ struct TuneEntry {
 };
 
 std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, int red,
-                     int nrhs, int npar);
+                     int nrhs, int npar, bool own_gauges);
 bool tune_find(const std::string &key, Shape *best);
 void tune_store(const std::string &key, const TuneEntry &e);
 bool tuning_enabled();
@@ -558,10 +581,18 @@ static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12
         }
     }
     if (!can_nr && !can_tg) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
-    const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar);
+    const std::string key = tune_key(a.g, prec, link12, DAG, XPAY, RED, a.nrhs, a.npar,
+                                     a.gtab != nullptr);
     {
+        // a recorded shape (this process or WL_TUNE_FILE) is clamped to what
+        // this launch allows: with a per-RHS gauge table every thread must own
+        // one RHS, since the kernel reads the links of its first RHS only
         Shape cached;
-        if (tune_find(key, &cached)) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, cached, s);
+        if (tune_find(key, &cached)) {
+            if (!can_nr) cached.nr = 1;
+            if (cached.tg < 0 || cached.tg >= a.ntile_t) cached.tg = 0;
+            return launch_nr<ST, NCL, DAG, XPAY, RED>(a, cached, s);
+        }
     }
     // is it safe to time the candidates on this call?
     bool safe = tuning_enabled();
@@ -702,6 +733,10 @@ static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Pha
     a.ksc = call.ksc;
     a.cmul = call.cmul;
     a.cpow = call.cpow;
+    a.twist = call.tx != 0.0 || call.ta != 0.0 || call.sx != 1.0;
+    a.tx = R(call.tx);
+    a.ta = R(call.ta);
+    a.sx = R(call.sx);
     const bool xpay = call.xs[call.first_par] != nullptr;
     return link12 ? launch_ncl<ST, 6>(a, call, prec, link12, call.dag, xpay, red, s)
                   : launch_ncl<ST, 9>(a, call, prec, link12, call.dag, xpay, red, s);

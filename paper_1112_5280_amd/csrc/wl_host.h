@@ -15,6 +15,7 @@ struct SolveIn {
     void *x;
     Geom g;
     double kappa;
+    double mu = 0.0;   // twisted mass (single solves only)
     Phases ph;
     double tol;
     int maxiter;

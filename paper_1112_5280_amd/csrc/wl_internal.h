@@ -288,6 +288,8 @@ enum Epi : int {
     kEpiBiAlpha,    // sum0,1 = <rhat, v>
     kEpiBiOmega,    // sum0,1 = <t, s>, sum2 = <t, t>
     kEpiBiRho,      // sum0 = ||r||^2, sum1,2 = <rhat, r>
+    kEpiBiResume,   // sum0 = ||r||^2, sum1,2 = <rhat, r> of a replaced residual
+    kEpiBiInitShadow,   // sum0 = ||r||^2, sum1,2 = <rhat, r> (rhat not r)
 };
 
 // Solver state in device memory (lives at the start of the workspace).
@@ -338,6 +340,8 @@ struct HopCall {
     const struct Scalars *ksc = nullptr;
     double cmul = 0.0;
     int cpow = 0;
+    // twisted mass: out = sx (1 + i tx g5) xs + c (1 + i ta g5) D in
+    double tx = 0.0, ta = 0.0, sx = 1.0;
 };
 hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
                       const HopCall &call, hipStream_t s);
@@ -345,6 +349,12 @@ hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
 hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // The autotuner's choices so far, one line per tuned batched-operator shape.
 std::string tuning_report();
+
+// Meson correlators (wl_meson.hip): 12 packed FP64 propagator columns ->
+// corr[16][Lt][2] on the device, through meson_workspace_bytes(g) of work
+size_t meson_workspace_bytes(const Geom &g);
+hipError_t launch_meson(const Geom &g, const void *props, int t0, double *corr, void *work,
+                        hipStream_t s);
 
 // Canonical complex128 <-> packed
 hipError_t launch_pack_gauge(const Geom &g, int prec, bool link12, const void *canon,
@@ -373,12 +383,16 @@ enum BlasOp : int {
     kOpAxpy,            // y += a x (a = host scalar)
     kOpCopyNorm2,       // y = x, sum0 = ||x||^2 (init of CG/BiCGStab)
     kOpCopy2Norm2,      // y = x, z = x, sum0 = ||x||^2
+    kOpNormDot,         // sum0 = ||y||^2, sum1,2 = <x, y>  (x = v0, y = v1)
+    kOpRandom,          // y = pseudo-random field, components in (-1, 1), seed = a
+    kOpTwist,           // y = a (1 + i b g5) x  (twisted-mass diagonal or its inverse)
 };
 struct BlasCall {
     int op;
     int npar;
     void *v[6];           // operand parity-0 blocks, meaning per op
     double a;             // host scalar for kOpAxpy
+    double b = 0.0;       // second host scalar (kOpTwist)
     Scalars *sc;          // RHS r reads sc[r]
     const int *skip;
     const Reduce *red;

@@ -139,6 +139,56 @@ __device__ inline void run_epilogue(int epi, const double *tot, Scalars *sc) {
         sc->rho[1] = n1;
         break;
     }
+    case kEpiBiInitShadow: {   // a fresh sequence whose shadow rhat is not r
+        const double rr = tot[0];
+        sc->rr = rr;
+        sc->rho[0] = tot[1];
+        sc->rho[1] = tot[2];
+        sc->alpha_c[0] = 1.0;
+        sc->alpha_c[1] = 0.0;
+        sc->omega[0] = 1.0;
+        sc->omega[1] = 0.0;
+        sc->beta_c[0] = 0.0;
+        sc->beta_c[1] = 0.0;
+        sc->iter = 0;
+        sc->status = WL_OK;
+        if (!finite(rr) || !finite(tot[1]) || !finite(tot[2])) {
+            sc->done = 1;
+            sc->status = WL_BREAKDOWN;
+        } else {
+            sc->done = rr <= sc->target;
+        }
+        break;
+    }
+    case kEpiBiResume: {  // the residual was replaced by a recomputed one:
+        // rho_new = <rhat, r> and beta = (rho_new / rho)(alpha / omega) for the
+        // direction update of the iteration whose end was the stop point
+        const double rr = tot[0];
+        const double n0 = tot[1], n1 = tot[2];
+        if (!finite(rr) || !finite(n0) || !finite(n1)) {
+            sc->done = 1;
+            sc->status = WL_BREAKDOWN;
+            break;
+        }
+        sc->rr = rr;
+        const double r0 = sc->rho[0], r1 = sc->rho[1];
+        const double w0 = sc->omega[0], w1 = sc->omega[1];
+        const double dr = r0 * r0 + r1 * r1, dw = w0 * w0 + w1 * w1;
+        if (!(dr > 0.0) || !(dw > 0.0) || !(n0 * n0 + n1 * n1 > 0.0)) {
+            sc->done = 1;
+            sc->status = WL_BREAKDOWN;
+            break;
+        }
+        const double q0 = (n0 * r0 + n1 * r1) / dr, q1 = (n1 * r0 - n0 * r1) / dr;
+        const double a0 = sc->alpha_c[0], a1 = sc->alpha_c[1];
+        const double s0 = (a0 * w0 + a1 * w1) / dw, s1 = (a1 * w0 - a0 * w1) / dw;
+        sc->beta_c[0] = q0 * s0 - q1 * s1;
+        sc->beta_c[1] = q0 * s1 + q1 * s0;
+        sc->rho[0] = n0;
+        sc->rho[1] = n1;
+        sc->done = rr <= sc->target;
+        break;
+    }
     default:
         break;
     }

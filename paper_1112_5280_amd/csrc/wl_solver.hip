@@ -19,9 +19,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <deque>
+#include <initializer_list>
+#include <map>
 #include <thread>
 #include <vector>
 
@@ -141,6 +145,11 @@ struct Space {
     // (sc[r].kappa); the hop coefficient is then cmul * kappa_r^cpow
     const void *const *gtab = nullptr;
     bool per_kappa = false;
+    // twisted mass: tw = 2 kappa mu (0: Wilson). The operator is then
+    // M = A - kappa D_W with A = 1 + i tw g5; its even-odd form is the Schur
+    // complement S = A - kappa^2 D_eo A^-1 D_oe, A^-1 = (1 - i tw g5)/(1 + tw^2),
+    // and the adjoints take -tw (A^dag = 1 - i tw g5, g5 D g5 = D^dag).
+    double tw = 0.0;
 
     // hop coefficient c = cmul * kappa^cpow, for the shared or per-RHS kappa
     void coef(HopCall &c, double cmul, int cpow) const {
@@ -178,6 +187,7 @@ struct Space {
             c.first_par = 0; c.npar = 2; c.dag = dag; c.skip = skip; c.red = rp;
             c.nrhs = nrhs; c.fstride = fstride;
             coef(c, -1.0, 1);
+            if (tw != 0.0) c.tx = dag ? -tw : tw;
             check(launch_hop(*g, prec, link12, ph, c, s));
         } else {
             HopCall c1{};
@@ -187,6 +197,10 @@ struct Space {
             c1.first_par = 1; c1.npar = 1; c1.dag = dag; c1.skip = skip;
             c1.nrhs = nrhs; c1.fstride = fstride;
             coef(c1, 1.0, 0);
+            if (tw != 0.0) {   // tmp = A^-1 D in  (adjoint: A^-dag D^dag in)
+                c1.c = 1.0 / (1.0 + tw * tw);
+                c1.ta = dag ? tw : -tw;
+            }
             check(launch_hop(*g, prec, link12, ph, c1, s));
             HopCall c2{};
             c2.gauge = gauge;
@@ -198,6 +212,7 @@ struct Space {
             c2.red = rp;
             c2.nrhs = nrhs; c2.fstride = fstride;
             coef(c2, -1.0, 2);
+            if (tw != 0.0) c2.tx = dag ? -tw : tw;   // A in - kappa^2 D tmp
             check(launch_hop(*g, prec, link12, ph, c2, s));
         }
         applies += 1;
@@ -205,17 +220,18 @@ struct Space {
 
     void blas(int op, void *v0, void *v1 = nullptr, void *v2 = nullptr, void *v3 = nullptr,
               void *v4 = nullptr, void *v5 = nullptr, int epi = kEpiNone, bool use_skip = true,
-              double a = 0.0) {
+              double a = 0.0, double b = 0.0) {
         const Reduce r = red(epi);
         BlasCall c{};
         c.op = op;
         c.npar = npar();
         c.v[0] = v0; c.v[1] = v1; c.v[2] = v2; c.v[3] = v3; c.v[4] = v4; c.v[5] = v5;
         c.a = a;
+        c.b = b;
         c.sc = sc;
         c.skip = use_skip ? &sc->done : nullptr;
         c.red = (op == kOpNorm2 || op == kOpXmy || op == kOpCgXR || op == kOpBiXR ||
-                 op == kOpCopyNorm2 || op == kOpCopy2Norm2) ? &r : nullptr;
+                 op == kOpCopyNorm2 || op == kOpCopy2Norm2 || op == kOpNormDot) ? &r : nullptr;
         c.nrhs = nrhs;
         c.fstride = fstride;
         check(launch_blas(*g, prec, c, s));
@@ -235,22 +251,79 @@ static int chunk_for(const Geom &g) { return g.Vh >= (1 << 18) ? 4 : 16; }
 
 // ---------------------------------------------------------------------------
 // Chunks of Krylov iterations, enqueued directly or -- with WL_GRAPH --
-// captured once into a HIP graph and replayed for every later chunk of the
-// same length. A chunk holds kernel launches only (no memset, no host work);
-// the host reads the status block between replays.
+// captured into a HIP graph and replayed. A chunk holds kernel launches only
+// (no memset, no host work); the host reads the status block between chunks.
+// Instantiated graphs are cached per host thread under a key of everything
+// their kernel arguments depend on (the loop kind, chunk length, stream,
+// operator, buffers and scalar block), so a later solve with the same
+// buffers replays them without capturing again.
 // ---------------------------------------------------------------------------
+using GraphKey = std::vector<uint64_t>;
+
+struct GraphCache {
+    static constexpr size_t kMax = 64;
+    std::map<GraphKey, hipGraphExec_t> execs;
+    std::deque<GraphKey> order;   // insertion order, for eviction
+    ~GraphCache() {
+        for (auto &kv : execs) (void)hipGraphExecDestroy(kv.second);
+    }
+    hipGraphExec_t find(const GraphKey &k) const {
+        auto it = execs.find(k);
+        return it == execs.end() ? nullptr : it->second;
+    }
+    void put(const GraphKey &k, hipGraphExec_t e) {
+        if (execs.size() >= kMax) {
+            auto it = execs.find(order.front());
+            if (it != execs.end()) {
+                (void)hipGraphExecDestroy(it->second);
+                execs.erase(it);
+            }
+            order.pop_front();
+        }
+        execs[k] = e;
+        order.push_back(k);
+    }
+};
+
+static GraphCache &graph_cache() {
+    thread_local GraphCache c;
+    return c;
+}
+
+static uint64_t bits_of(double v) {
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+
+// The key of a chunk loop of kind `tag` on space k over the given vectors
+static GraphKey chunk_key(int tag, const Space &k, std::initializer_list<const void *> vecs) {
+    GraphKey key{uint64_t(tag), uint64_t(reinterpret_cast<uintptr_t>(k.s)), uint64_t(k.prec),
+                 uint64_t(k.link12), uint64_t(k.eo), uint64_t(k.nrhs), uint64_t(k.fstride),
+                 uint64_t(reinterpret_cast<uintptr_t>(k.gauge)),
+                 uint64_t(reinterpret_cast<uintptr_t>(k.gtab)), uint64_t(k.per_kappa),
+                 bits_of(k.kappa), bits_of(k.tw),
+                 uint64_t(reinterpret_cast<uintptr_t>(k.sc)),
+                 uint64_t(reinterpret_cast<uintptr_t>(k.partials)),
+                 uint64_t(reinterpret_cast<uintptr_t>(k.tmp))};
+    for (int mu = 0; mu < 4; ++mu) {
+        key.push_back(uint64_t(k.g->L[mu]));
+        key.push_back(bits_of(k.ph.re[mu]));
+        key.push_back(bits_of(k.ph.im[mu]));
+    }
+    for (const void *v : vecs) key.push_back(uint64_t(reinterpret_cast<uintptr_t>(v)));
+    return key;
+}
+
 struct ChunkRunner {
     hipStream_t s;
     bool graph;
-    int captured_n = -1;
-    hipGraphExec_t exec = nullptr;
+    GraphKey key;
 
-    ChunkRunner(hipStream_t s_, bool graph_) : s(s_), graph(graph_) {}
+    ChunkRunner(hipStream_t s_, bool graph_, GraphKey key_ = {})
+        : s(s_), graph(graph_), key(std::move(key_)) {}
     ChunkRunner(const ChunkRunner &) = delete;
     ChunkRunner &operator=(const ChunkRunner &) = delete;
-    ~ChunkRunner() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-    }
 
     template <class F>
     void run(int n, F &&enqueue) {
@@ -258,12 +331,11 @@ struct ChunkRunner {
             enqueue(n);
             return;
         }
-        if (n != captured_n) {
-            if (exec) {
-                (void)hipGraphExecDestroy(exec);
-                exec = nullptr;
-                captured_n = -1;
-            }
+        GraphKey k = key;
+        k.push_back(uint64_t(n));
+        GraphCache &cache = graph_cache();
+        hipGraphExec_t exec = cache.find(k);
+        if (!exec) {
             check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             hipGraph_t gr = nullptr;
             try {
@@ -277,7 +349,7 @@ struct ChunkRunner {
             const hipError_t e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
             (void)hipGraphDestroy(gr);
             check(e);
-            captured_n = n;
+            cache.put(k, exec);
         }
         check(hipGraphLaunch(exec, s));
     }
@@ -321,7 +393,7 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
     const int chunk = chunk_for(*k.g);
     int done_it = 0;
     Scalars h = read_scalars(k.sc, k.s);
-    ChunkRunner runner(k.s, k.graph);
+    ChunkRunner runner(k.s, k.graph, chunk_key(1, k, {x, r, p, t, q}));
     while (!h.done && done_it < maxit) {
         const int n = std::min(chunk, maxit - done_it);
         runner.run(n, [&](int m) {
@@ -404,7 +476,7 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
     reload(rr);
     k32.blas(kOpCopyNorm2, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
     int its = 0, stale = 0;
-    ChunkRunner runner(k32.s, k32.graph);
+    ChunkRunner runner(k32.s, k32.graph, chunk_key(2, k32, {lo.p, lo.t, lo.q, lo.x, lo.r}));
     while (its < maxit) {
         Scalars h = read_scalars(k32.sc, k32.s);
         double best = h.rr;
@@ -468,12 +540,25 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
 // ---------------------------------------------------------------------------
 // BiCGStab core: iterate on A x = rhs until ||r||^2 <= target
 // ---------------------------------------------------------------------------
+// The shadow vector of a fresh BiCGStab sequence: rhat = r, or (after a
+// breakdown) a pseudo-random field of the given nonzero seed.
+static void bicg_shadow(Space &k, void *r, void *rh, uint64_t seed) {
+    if (!seed) {
+        k.blas(kOpCopyNorm2, r, rh, nullptr, nullptr, nullptr, nullptr, kEpiBiInit, false);
+        return;
+    }
+    k.blas(kOpRandom, rh, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false,
+           double(seed));
+    k.blas(kOpNormDot, rh, r, nullptr, nullptr, nullptr, nullptr, kEpiBiInitShadow, false);
+}
+
 static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *rh, void *p,
-                            void *v, void *sv, void *t, double target, int maxit) {
+                            void *v, void *sv, void *t, double target, int maxit,
+                            uint64_t shadow_seed) {
     check(launch_set_target(k.sc, target, k.s));
     k.apply(x, r, false, kEpiNone, nullptr, nullptr);
     k.blas(kOpXmy, const_cast<void *>(rhs), r, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
-    k.blas(kOpCopyNorm2, r, rh, nullptr, nullptr, nullptr, nullptr, kEpiBiInit, false);
+    bicg_shadow(k, r, rh, shadow_seed);
     k.blas(kOpZero, p, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
     k.blas(kOpZero, v, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
     const int chunk = chunk_for(*k.g);
@@ -483,7 +568,7 @@ static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *r
     double best = h.rr;
     int best_it = 0;
     bool stalled = false;
-    ChunkRunner runner(k.s, k.graph);
+    ChunkRunner runner(k.s, k.graph, chunk_key(3, k, {x, r, rh, p, v, sv, t}));
     while (!h.done && h.iter < maxit) {
         const int n = std::min(chunk, maxit - h.iter);
         runner.run(n, [&](int m) {
@@ -513,13 +598,145 @@ static CoreResult bicg_core(Space &k, const void *rhs, void *x, void *r, void *r
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-precision BiCGStab with reliable updates (Sleijpen-van der Vorst): one
+// BiCGStab sequence in the low-precision space klo on (r, rhat, p, v, s, t,
+// x_lo). Once ||r||^2 has dropped by delta^2 since the last update (the device
+// loop stops itself there, right after the x, r update of an iteration), x_lo
+// is added to the FP64 solution, the residual rhs - A x is recomputed in FP64
+// and replaces r, and the sequence resumes: rho = <rhat, r> of the replaced
+// residual gives the direction update of that iteration, with p, v, rhat,
+// alpha and omega kept. A sequence that breaks down or stalls (no 1 %
+// improvement of its best residual within kStallWindow iterations) is folded
+// into x as well, and the core returns to the caller, which restarts it from
+// the new FP64 residual with a fresh shadow vector, as for the FP64 solve.
+// ---------------------------------------------------------------------------
+struct BiLoVecs {
+    void *r, *rh, *p, *v, *s, *t, *x;
+};
+
+// residual reduction between reliable updates (WL_DELTA_BI_F32 / _F16 override)
+static double reliable_delta_bicg(int prec) {
+    const char *v = std::getenv(prec == WL_F16S ? "WL_DELTA_BI_F16" : "WL_DELTA_BI_F32");
+    const double d = v ? std::atof(v) : 0.0;
+    if (d > 0.0 && d < 1.0) return d;
+    return prec == WL_F16S ? 0.3 : 0.1;
+}
+
+static CoreResult bicg_reliable(Space &k64, Space &klo, const void *rhs, void *x, void *r64,
+                                const BiLoVecs &lo, double target, double delta, int maxit,
+                                uint64_t shadow_seed) {
+    const int npar = k64.npar();
+    const int chunk = chunk_for(*k64.g);
+    // r64 = rhs - A x in FP64; returns ||r64||^2
+    auto residual64 = [&]() {
+        k64.apply(x, r64, false, kEpiNone, nullptr, nullptr);
+        k64.blas(kOpXmy, const_cast<void *>(rhs), r64, nullptr, nullptr, nullptr, nullptr,
+                 kEpiNone, false);
+        return read_scalars(k64.sc, k64.s).sums[0];
+    };
+    // r_lo = r64, x_lo = 0, and the device stop point delta^2 ||r||^2
+    auto reload = [&](double rr) {
+        check(launch_convert_spinor(*k64.g, npar, WL_F64, r64, klo.prec, lo.r, k64.s));
+        klo.blas(kOpZero, lo.x, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+        check(launch_set_target(klo.sc, std::max(target, delta * delta * rr), klo.s));
+    };
+    CoreResult res{0, WL_NOCONV, 0.0, 0};
+    double rr = residual64();
+    res.rr = rr;
+    if (!std::isfinite(rr)) {
+        res.status = WL_BREAKDOWN;
+        return res;
+    }
+    if (rr <= target) {
+        res.status = WL_OK;
+        return res;
+    }
+    // a fresh sequence: rhat = r (or a pseudo-random shadow), p = v = 0
+    reload(rr);
+    bicg_shadow(klo, lo.r, lo.rh, shadow_seed);
+    klo.blas(kOpZero, lo.p, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    klo.blas(kOpZero, lo.v, nullptr, nullptr, nullptr, nullptr, nullptr, kEpiNone, false);
+    int its = 0, stale = 0;
+    ChunkRunner runner(klo.s, klo.graph,
+                       chunk_key(4, klo, {lo.r, lo.rh, lo.p, lo.v, lo.s, lo.t, lo.x}));
+    while (its < maxit) {
+        Scalars h = read_scalars(klo.sc, klo.s);
+        double best = h.rr;
+        int best_it = h.iter;
+        bool stalled = false;
+        while (!h.done && its + h.iter < maxit) {
+            const int n = std::min(chunk, maxit - its - h.iter);
+            runner.run(n, [&](int m) {
+                for (int it = 0; it < m; ++it) {
+                    const int *skip = &klo.sc->done;
+                    klo.blas(kOpBiP, lo.r, lo.p, lo.v);
+                    klo.apply(lo.p, lo.v, false, kEpiBiAlpha, lo.rh, skip);
+                    klo.blas(kOpBiS, lo.r, lo.v, lo.s);
+                    klo.apply(lo.s, lo.t, false, kEpiBiOmega, nullptr, skip);
+                    klo.blas(kOpBiXR, lo.x, lo.p, lo.s, lo.t, lo.r, lo.rh, kEpiBiRho);
+                }
+            });
+            h = read_scalars(klo.sc, klo.s);
+            if (h.rr < 0.99 * best) {
+                best = h.rr;
+                best_it = h.iter;
+            } else if (h.iter - best_it > kStallWindow) {
+                stalled = true;
+                break;
+            }
+        }
+        its += h.iter;
+        // reliable update: x += x_lo in FP64, the FP64 residual replaces r
+        check(launch_accum_lo(*k64.g, npar, klo.prec, lo.x, x, k64.s));
+        const double rr_new = residual64();
+        res.updates += 1;
+        res.rr = rr_new;
+        if (!std::isfinite(rr_new)) {
+            res.status = WL_BREAKDOWN;
+            break;
+        }
+        if (rr_new <= target) {
+            res.status = WL_OK;
+            break;
+        }
+        if (stalled) {
+            res.status = WL_STAGNATED;
+            break;
+        }
+        if (!h.done || h.status != WL_OK) {   // out of iterations, or broken down
+            res.status = h.done ? h.status : WL_NOCONV;
+            break;
+        }
+        stale = rr_new < 0.5 * rr ? 0 : stale + 1;
+        if (stale > 8) {
+            res.status = WL_STAGNATED;
+            break;
+        }
+        rr = rr_new;
+        reload(rr);
+        klo.blas(kOpNormDot, lo.rh, lo.r, nullptr, nullptr, nullptr, nullptr, kEpiBiResume,
+                 false);
+    }
+    res.iters = its;
+    return res;
+}
+
+// ---------------------------------------------------------------------------
 // Even-odd source preparation and reconstruction (in the space's precision)
 // ---------------------------------------------------------------------------
-// bhat_e = b_e + kappa D_eo b_o
+// bhat_e = b_e + kappa D_eo b_o  (twisted mass: b_e + kappa D_eo A^-1 b_o,
+// with A^-1 b_o formed in the space's intermediate block)
 static void eo_source(Space &k, const void *b_full, void *bhat_e) {
     HopCall c{};
     c.gauge = k.gauge;
     c.in[1] = k.par(b_full, 1);
+    if (k.tw != 0.0) {
+        Space one = k;
+        one.eo = true;   // one parity block per field
+        one.blas(kOpTwist, const_cast<void *>(k.par(b_full, 1)), k.tmp, nullptr, nullptr,
+                 nullptr, nullptr, kEpiNone, false, 1.0 / (1.0 + k.tw * k.tw), -k.tw);
+        c.in[1] = k.tmp;
+    }
     c.xs[0] = b_full;
     c.out[0] = bhat_e;
     c.first_par = 0; c.npar = 1; c.dag = false;
@@ -538,6 +755,12 @@ static void eo_reconstruct(Space &k, const void *b_full, void *x_full) {
     c.first_par = 1; c.npar = 1; c.dag = false;
     c.nrhs = k.nrhs; c.fstride = k.fstride;
     k.coef(c, 1.0, 1);
+    if (k.tw != 0.0) {   // x_o = A^-1 (b_o + kappa D_oe x_e)
+        const double s = 1.0 / (1.0 + k.tw * k.tw);
+        c.c *= s;
+        c.sx = s;
+        c.tx = c.ta = -k.tw;
+    }
     check(launch_hop(*k.g, k.prec, k.link12, k.ph, c, k.s));
 }
 
@@ -617,6 +840,7 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
 
     Space full64{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, false, in.s, ws.sc,
                  ws.partials, nullptr};
+    full64.tw = 2.0 * in.kappa * in.mu;
     wl_solve_stats out{};
     double flops = 0, bytes = 0;
     int status = WL_NOCONV;
@@ -641,152 +865,141 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
             double r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
             flops += tr.flops;
             bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0;
-            int total_it = 0, restarts = 0, reliable = 0;
+            int total_it = 0, restarts = 0, reliable = 0, fp64_it = 0;
             double best_r2 = r2;
             int since_best = 0;
 
-            if (!(mixed && bicg)) {
-                // Krylov on the caller's x (even block for eo): plain FP64, or
-                // FP32 iterations with reliable FP64 updates (mixed CG)
-                Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, ws.sc,
-                        ws.partials, ws.v64[7]};
-                const int lo = lo_prec(in.flags);
-                Space k32{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
-                          ws.partials, ws.v32[7]};
-                k.graph = k32.graph = graph;
-                if (mixed)
-                    check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
-                void *rhs = const_cast<void *>(in.b);
-                if (eo) {
-                    eo_source(k, in.b, ws.v64[5]);
-                    rhs = ws.v64[5];
+            // Krylov on the caller's x (even block for eo): plain FP64, or
+            // low-precision iterations with reliable FP64 updates (mixed)
+            Space k{&g, WL_F64, link12, in.ph, in.gauge, in.kappa, eo, in.s, ws.sc,
+                    ws.partials, ws.v64[7]};
+            const int lo = lo_prec(in.flags);
+            Space k32{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
+                      ws.partials, ws.v32[7]};
+            k.graph = k32.graph = graph;
+            k.tw = k32.tw = full64.tw;
+            if (mixed)
+                check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
+            void *rhs = const_cast<void *>(in.b);
+            if (eo) {
+                eo_source(k, in.b, ws.v64[5]);
+                rhs = ws.v64[5];
+            }
+            double mb2 = 0;
+            if (!bicg) {   // ||A^dag rhs||^2 sets the scale of the CG target
+                k.apply(rhs, ws.v64[2], true, kEpiNone, nullptr, nullptr);
+                mb2 = k.norm2(ws.v64[2]);
+            }
+            const double rhs2 = bicg ? k.norm2(rhs) : 0.0;
+            double eta = in.tol;
+            // a mixed BiCGStab whose low-precision sequence stops making
+            // progress continues in FP64 from its best iterate
+            bool fp64_bicg = false;
+            // a BiCGStab pass that broke down without any progress is tried
+            // again from the same iterate with a pseudo-random shadow vector
+            // instead of rhat = r (a Krylov scalar vanished or overflowed for
+            // that shadow); a few such retries in a row are allowed
+            uint64_t shadow_seed = 0;
+            int breakdowns = 0;
+            const bool trace = std::getenv("WL_TRACE") != nullptr;
+            while (true) {
+                if (r2 <= tol2) { status = WL_OK; break; }
+                if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
+                if (mixed && bicg && !fp64_bicg && since_best > 3) {
+                    fp64_bicg = true;
+                    since_best = 0;
                 }
-                double mb2 = 0;
-                if (!bicg) {   // ||A^dag rhs||^2 sets the scale of the CG target
-                    k.apply(rhs, ws.v64[2], true, kEpiNone, nullptr, nullptr);
-                    mb2 = k.norm2(ws.v64[2]);
+                if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
+                // keep the current iterate: if this Krylov pass leaves x
+                // worse (a stalled BiCGStab), the solve returns this one
+                full64.blas(kOpCopy, in.x, ws.v64[8], nullptr, nullptr, nullptr, nullptr,
+                            kEpiNone, false);
+                const double r2_prev = r2;
+                CoreResult cr;
+                const int left = in.maxiter - total_it;
+                bool lo_iters = mixed;
+                if (bicg && (!mixed || fp64_bicg)) {
+                    cr = bicg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2],
+                                   ws.v64[3], ws.v64[4], ws.v64[6], eta * eta * rhs2, left,
+                                   shadow_seed);
+                    lo_iters = false;
+                    if (mixed) fp64_it += cr.iters;
+                } else if (bicg) {
+                    const BiLoVecs lv{ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3],
+                                      ws.v32[4], ws.v32[5], ws.v32[6]};
+                    cr = bicg_reliable(k, k32, rhs, in.x, ws.v64[0], lv, eta * eta * rhs2,
+                                       reliable_delta_bicg(lo), left, shadow_seed);
+                } else if (mixed) {
+                    const LoVecs lv{ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3], ws.v32[6]};
+                    cr = cg_reliable(k, k32, rhs, in.x, ws.v64[0], ws.v64[2], lv,
+                                     eta * eta * mb2, reliable_delta(lo), left);
+                } else {
+                    cr = cg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2], ws.v64[3],
+                                 eta * eta * mb2, left);
                 }
-                const double rhs2 = bicg ? k.norm2(rhs) : 0.0;
-                double eta = in.tol;
-                while (true) {
-                    if (r2 <= tol2) { status = WL_OK; break; }
-                    if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
-                    if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
-                    // keep the current iterate: if this Krylov pass leaves x
-                    // worse (a stalled BiCGStab), the solve returns this one
-                    full64.blas(kOpCopy, in.x, ws.v64[8], nullptr, nullptr, nullptr, nullptr,
+                if (lo_iters) {   // cost of the FP64 residual replacements
+                    const Cost u = apply_cost(g, WL_F64, link12, eo);
+                    const double Vs = eo ? g.Vh : 2.0 * g.Vh;
+                    const double napply = bicg ? 1 : 2;
+                    flops += cr.updates * napply * u.flops;
+                    bytes += cr.updates * (napply * u.bytes +
+                                           Vs * (6 * 192.0 + 3 * site_bytes(lo)));
+                    reliable += cr.updates;
+                }
+                total_it += cr.iters;
+                const Cost c = iter_cost(g, lo_iters ? lo : WL_F64, link12, eo, bicg);
+                flops += c.flops * cr.iters;
+                bytes += c.bytes * cr.iters;
+                if (eo) eo_reconstruct(k, in.b, in.x);
+                r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
+                flops += tr.flops;
+                bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
+                if (trace)
+                    std::fprintf(stderr, "[wl] %s pass %d (%s%s): %d iterations, %d updates, "
+                                 "core status %d, true residual %.3e -> %.3e\n",
+                                 bicg ? "bicgstab" : "cg", restarts,
+                                 lo_iters ? "low precision" : "fp64",
+                                 shadow_seed ? ", random shadow" : "", cr.iters, cr.updates,
+                                 cr.status, std::sqrt(r2_prev / b2), std::sqrt(r2 / b2));
+                if (!(r2 < r2_prev)) {   // no progress: restore the kept iterate
+                    full64.blas(kOpCopy, ws.v64[8], in.x, nullptr, nullptr, nullptr, nullptr,
                                 kEpiNone, false);
-                    const double r2_prev = r2;
-                    CoreResult cr;
-                    const int left = in.maxiter - total_it;
-                    if (bicg) {
-                        cr = bicg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2],
-                                       ws.v64[3], ws.v64[4], ws.v64[6], eta * eta * rhs2, left);
-                    } else if (mixed) {
-                        const LoVecs lv{ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3], ws.v32[6]};
-                        cr = cg_reliable(k, k32, rhs, in.x, ws.v64[0], ws.v64[2], lv,
-                                         eta * eta * mb2, reliable_delta(lo), left);
-                        const Cost u = apply_cost(g, WL_F64, link12, eo);
-                        const double Vs = eo ? g.Vh : 2.0 * g.Vh;
-                        flops += cr.updates * 2 * u.flops;
-                        bytes += cr.updates * (2 * u.bytes +
-                                               Vs * (6 * 192.0 + 3 * site_bytes(lo)));
-                        reliable += cr.updates;
-                    } else {
-                        cr = cg_core(k, rhs, in.x, ws.v64[0], ws.v64[1], ws.v64[2], ws.v64[3],
-                                     eta * eta * mb2, left);
-                    }
-                    total_it += cr.iters;
-                    const Cost c = iter_cost(g, mixed ? lo : WL_F64, link12, eo, bicg);
-                    flops += c.flops * cr.iters;
-                    bytes += c.bytes * cr.iters;
-                    if (eo) eo_reconstruct(k, in.b, in.x);
                     r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
                     flops += tr.flops;
                     bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
-                    if (!(r2 < r2_prev)) {   // no progress: restore the kept iterate, stop
-                        full64.blas(kOpCopy, ws.v64[8], in.x, nullptr, nullptr, nullptr, nullptr,
-                                    kEpiNone, false);
-                        r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
-                        flops += tr.flops;
-                        bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
-                        status = !std::isfinite(r2) ? WL_BREAKDOWN
-                               : (cr.status == WL_BREAKDOWN ? WL_BREAKDOWN : WL_STAGNATED);
-                        if (r2 <= tol2) status = WL_OK;
-                        break;
+                    if (mixed && bicg && !fp64_bicg && std::isfinite(r2)) {
+                        fp64_bicg = true;   // go on in FP64 from the kept iterate
+                        since_best = 0;
+                        ++restarts;
+                        continue;
                     }
-                    if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
-                    else ++since_best;
-                    if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
-                    if (r2 <= tol2) { status = WL_OK; break; }
-                    ++restarts;
-                    if (cr.status != WL_BREAKDOWN) {
-                        const double rho = std::sqrt(r2 / b2);
-                        eta = std::max(eta * (in.tol / rho) * 0.5, 1e-17);
+                    if (bicg && cr.status == WL_BREAKDOWN && breakdowns < 3 &&
+                        std::isfinite(r2)) {
+                        // retry from the kept iterate with a pseudo-random shadow
+                        ++breakdowns;
+                        shadow_seed = 0x5eed0000ull + uint64_t(restarts) + 1;
+                        ++restarts;
+                        continue;
                     }
+                    status = !std::isfinite(r2) ? WL_BREAKDOWN
+                           : (cr.status == WL_BREAKDOWN ? WL_BREAKDOWN : WL_STAGNATED);
+                    if (r2 <= tol2) status = WL_OK;
+                    break;
                 }
-            } else {
-                // FP64 defect correction around FP32 BiCGStab solves of M e = r;
-                // each inner solve aims at 1e-5 relative, or less when that
-                // would overshoot the final tolerance
-                const int lo = lo_prec(in.flags);
-                Space k{&g, lo, link12, in.ph, ws.gauge32, in.kappa, eo, in.s, ws.sc,
-                        ws.partials, ws.v32[7]};
-                k.graph = graph;
-                check(launch_convert_gauge(g, link12, in.gauge, lo, ws.gauge32, in.s));
-                // the precision floor of the inner solve: FP16 storage cannot
-                // reach 1e-5 relative
-                const double floor = lo == WL_F16S ? 1e-2 : 1e-5;
-                while (true) {
-                    const double delta = std::max(floor, 0.3 * std::sqrt(tol2 / r2));
-                    if (r2 <= tol2) { status = WL_OK; break; }
-                    if (total_it >= in.maxiter) { status = WL_NOCONV; break; }
-                    if (restarts > kMaxRestarts || since_best > 3) { status = WL_STAGNATED; break; }
-                    // r64 (in v64[6]) -> r_lo (v32[5]); e_lo (v32[6]) = 0
-                    check(launch_convert_spinor(g, 2, WL_F64, ws.v64[6], lo, ws.v32[5], in.s));
-                    k.eo = false;
-                    k.blas(kOpZero, ws.v32[6], nullptr, nullptr, nullptr, nullptr, nullptr,
-                           kEpiNone, false);
-                    k.eo = eo;
-                    void *rhs = ws.v32[5];
-                    if (eo) {
-                        eo_source(k, ws.v32[5], ws.v32[4]);
-                        rhs = ws.v32[4];
-                    }
-                    const int left = in.maxiter - total_it;
-                    const double rhs2 = k.norm2(rhs);
-                    const CoreResult cr =
-                        bicg_core(k, rhs, ws.v32[6], ws.v32[0], ws.v32[1], ws.v32[2], ws.v32[3],
-                                  ws.v32[8], ws.v32[9], delta * delta * rhs2, left);
-                    total_it += cr.iters;
-                    const Cost c = iter_cost(g, lo, link12, eo, bicg);
-                    flops += c.flops * cr.iters;
-                    bytes += c.bytes * cr.iters;
-                    if (eo) eo_reconstruct(k, ws.v32[5], ws.v32[6]);
-                    // keep the current iterate: a correction from an inner solve
-                    // that stalled may make x worse, and x must stay the best
-                    full64.blas(kOpCopy, in.x, ws.v64[8], nullptr, nullptr, nullptr, nullptr,
-                                kEpiNone, false);
-                    check(launch_accum_lo(g, 2, lo, ws.v32[6], in.x, in.s));
-                    const double r2_prev = r2;
-                    r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
-                    flops += tr.flops;
-                    bytes += tr.bytes + 3.0 * 2 * g.Vh * 192.0 + 2.0 * 2 * g.Vh * 192.0;
-                    ++restarts;
-                    if (!(r2 < r2_prev)) {   // rejected: restore x (and r64), stop
-                        full64.blas(kOpCopy, ws.v64[8], in.x, nullptr, nullptr, nullptr, nullptr,
-                                    kEpiNone, false);
-                        r2 = true_res2(full64, in.b, in.x, ws.v64[6]);
-                        flops += tr.flops;
-                        bytes += tr.bytes + 5.0 * 2 * g.Vh * 192.0;
-                        status = std::isfinite(r2) ? WL_STAGNATED : WL_BREAKDOWN;
-                        break;
-                    }
-                    if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
-                    else ++since_best;
+                breakdowns = 0;   // progress: the next pass restarts with rhat = r
+                shadow_seed = 0;
+                if (r2 < best_r2 * 0.5) { best_r2 = r2; since_best = 0; }
+                else ++since_best;
+                if (!std::isfinite(r2)) { status = WL_BREAKDOWN; break; }
+                if (r2 <= tol2) { status = WL_OK; break; }
+                ++restarts;
+                if (cr.status != WL_BREAKDOWN) {
+                    const double rho = std::sqrt(r2 / b2);
+                    eta = std::max(eta * (in.tol / rho) * 0.5, 1e-17);
                 }
             }
             out.iterations = total_it;
+            out.fp64_iterations = mixed ? fp64_it : total_it;
             out.restarts = restarts;
             out.reliable_updates = reliable;
             out.true_res = std::sqrt(r2 / b2);
@@ -868,7 +1081,7 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
         return true;
     };
     int done_it = 0;
-    ChunkRunner runner(k.s, k.graph);
+    ChunkRunner runner(k.s, k.graph, chunk_key(5, k, {x, r, p, t, q}));
     while (!all_done() && done_it < maxit) {
         const int n = std::min(chunk, maxit - done_it);
         runner.run(n, [&](int m) {
@@ -947,7 +1160,7 @@ static void cg_reliable_batch(Space &k64, Space &k32, const void *rhs, void *x, 
     reload();
     k32.blas(kOpCopyNorm2, lo.r, lo.p, nullptr, nullptr, nullptr, nullptr, kEpiCgInit, false);
     Scalars h[kMaxBatch];
-    ChunkRunner runner(k32.s, k32.graph);
+    ChunkRunner runner(k32.s, k32.graph, chunk_key(6, k32, {lo.p, lo.t, lo.q, lo.x, lo.r}));
     while (true) {
         read_scalars_n(k32.sc, n, k32.s, h);
         auto running = [&](int r) { return active[r] && !h[r].done && its[r] + h[r].iter < maxit; };
@@ -1227,6 +1440,7 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
             st[r] = wl_solve_stats{};
             st[r].status = status[r];
             st[r].iterations = total[r];
+            st[r].fp64_iterations = mixed ? 0 : total[r];
             st[r].restarts = restarts[r];
             st[r].reliable_updates = updates[r];
             st[r].true_res = b2[r] > 0.0 ? std::sqrt(r2[r] / b2[r]) : 0.0;

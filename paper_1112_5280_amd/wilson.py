@@ -47,7 +47,9 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "solve_cg", "solve_bicgstab", "wilson_dslash_batch", "solve_cg_batch",
            "wl_problems_workspace_bytes", "solve_cg_problems",
            "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
-           "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy")
+           "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy",
+           "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
+           "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators")
 
 
 class WilsonError(RuntimeError):
@@ -60,10 +62,11 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
                 ("true_res", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("fp64_iterations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class ServerConfig(ctypes.Structure):
@@ -109,6 +112,17 @@ def _load():
         f.argtypes = [P, P, P, P, D, P, D, I32, U32, P, SZ,
                       ctypes.POINTER(SolveStats), P]
         f.restype = ctypes.c_int
+    lib.wilson_dslash_tm.argtypes = [P, P, P, P, D, D, P, U32, P]
+    lib.wilson_dslash_tm.restype = ctypes.c_int
+    lib.wilson_dslash_eo_tm.argtypes = [P, P, P, P, D, D, P, I32, U32, P]
+    lib.wilson_dslash_eo_tm.restype = ctypes.c_int
+    for f in (lib.solve_cg_tm, lib.solve_bicgstab_tm):
+        f.argtypes = [P, P, P, P, D, D, P, D, I32, U32, P, SZ, ctypes.POINTER(SolveStats), P]
+        f.restype = ctypes.c_int
+    lib.wl_meson_workspace_bytes.argtypes = [P]
+    lib.wl_meson_workspace_bytes.restype = SZ
+    lib.wl_meson_correlators.argtypes = [P, P, I32, P, P, SZ, P]
+    lib.wl_meson_correlators.restype = ctypes.c_int
     lib.wilson_dslash_batch.argtypes = [P, P, P, I32, P, D, P, U32, P]
     lib.wilson_dslash_batch.restype = ctypes.c_int
     lib.solve_cg_batch.argtypes = [P, P, P, I32, P, D, P, D, I32, U32, P, SZ,
@@ -266,18 +280,22 @@ def wilson_dslash(gauge, inp, out, dims, kappa, phases=ANTIPERIODIC_T, flags=F64
 
 def wilson_dslash_eo(gauge, inp, out, dims, kappa, out_parity, phases=ANTIPERIODIC_T,
                      flags=F64, stream=None):
-    """HOP: out_p = D_{p,1-p} in_{1-p}; default: out_p = Mhat_p in_p (half fields)."""
+    """HOP: out_p = D_{p,1-p} in_{1-p} (half fields). Default: the Schur operator,
+    in_p a half field and out a FULL field whose parity-p block receives
+    Mhat_p in_p and whose other block receives the intermediate D_{1-p,p} in_p."""
     return _check(lib.wilson_dslash_eo(_ptr(gauge), _ptr(inp), _ptr(out), _dims(dims),
                                        float(kappa), _phases(phases), int(out_parity),
                                        flags, _stream(stream)), "wilson_dslash_eo")
 
 
-def _solve(fn, name, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work, stream):
+def _solve(fn, name, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work, stream,
+           mu=None):
     need = workspace_bytes(dims, flags)
     if work is None:
         work = torch.empty(max(need, 1), dtype=torch.uint8, device=b.device)
     st = SolveStats()
-    code = fn(_ptr(gauge), _ptr(b), _ptr(x), _dims(dims), float(kappa), _phases(phases),
+    extra = () if mu is None else (float(mu),)
+    code = fn(_ptr(gauge), _ptr(b), _ptr(x), _dims(dims), float(kappa), *extra, _phases(phases),
               float(tol), int(maxiter), flags, _ptr(work), work.numel(), ctypes.byref(st),
               _stream(stream))
     _check(code, name)
@@ -300,6 +318,52 @@ def solve_bicgstab(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
     """BiCGStab solve of M x = b (packed FP64 b, x); returns the stats dict."""
     return _solve(lib.solve_bicgstab, "solve_bicgstab", gauge, b, x, dims, kappa, phases,
                   tol, maxiter, flags, work, stream)
+
+
+def wilson_dslash_tm(gauge, inp, out, dims, kappa, mu, phases=ANTIPERIODIC_T, flags=F64,
+                     stream=None):
+    """Twisted-mass operator M(mu) (or M(mu)^dag, or D_W with HOP); asynchronous."""
+    return _check(lib.wilson_dslash_tm(_ptr(gauge), _ptr(inp), _ptr(out), _dims(dims),
+                                       float(kappa), float(mu), _phases(phases), flags,
+                                       _stream(stream)), "wilson_dslash_tm")
+
+
+def wilson_dslash_eo_tm(gauge, inp, out, dims, kappa, mu, out_parity, phases=ANTIPERIODIC_T,
+                        flags=F64, stream=None):
+    """Twisted-mass even-odd operator: HOP as wilson_dslash_eo; default the Schur
+    complement A - kappa^2 D A^-1 D into the parity-p block of the full field out."""
+    return _check(lib.wilson_dslash_eo_tm(_ptr(gauge), _ptr(inp), _ptr(out), _dims(dims),
+                                          float(kappa), float(mu), _phases(phases),
+                                          int(out_parity), flags, _stream(stream)),
+                  "wilson_dslash_eo_tm")
+
+
+def solve_cg_tm(gauge, b, x, dims, kappa, mu, phases=ANTIPERIODIC_T, tol=1e-10,
+                maxiter=100000, flags=F64, work=None, stream=None):
+    """CGNR solve of M(mu) x = b (twisted mass); returns the stats dict."""
+    return _solve(lib.solve_cg_tm, "solve_cg_tm", gauge, b, x, dims, kappa, phases, tol,
+                  maxiter, flags, work, stream, mu=mu)
+
+
+def solve_bicgstab_tm(gauge, b, x, dims, kappa, mu, phases=ANTIPERIODIC_T, tol=1e-10,
+                      maxiter=100000, flags=F64, work=None, stream=None):
+    """BiCGStab solve of M(mu) x = b (twisted mass); returns the stats dict."""
+    return _solve(lib.solve_bicgstab_tm, "solve_bicgstab_tm", gauge, b, x, dims, kappa,
+                  phases, tol, maxiter, flags, work, stream, mu=mu)
+
+
+def meson_correlators(props, dims, t0=0, work=None, stream=None):
+    """Eq. 1's C_Gamma(t) for the 16 Gamma_n from 12 propagator columns (a batch
+    of packed FP64 full spinors, field 3 b + c); returns a complex128 tensor
+    [16, Lt] on the device (t counted from t0)."""
+    Lt = int(dims[3])
+    corr = torch.empty((16, Lt, 2), dtype=torch.float64, device=props.device)
+    if work is None:
+        work = torch.empty(max(int(lib.wl_meson_workspace_bytes(_dims(dims))), 1),
+                           dtype=torch.uint8, device=props.device)
+    _check(lib.wl_meson_correlators(_ptr(props), _dims(dims), int(t0), _ptr(corr), _ptr(work),
+                                    work.numel(), _stream(stream)), "wl_meson_correlators")
+    return torch.view_as_complex(corr)
 
 
 def empty_batch(dims, nrhs, flags=F64, device="cuda"):

@@ -161,3 +161,4 @@ def test_stream_copy_checks(w):
     assert lib.wl_stream_copy(_p(4104), _p(8192), 64, None) == -1       # misaligned
     assert lib.wl_stream_copy(_p(4096), _p(4096 + 32), 64, None) == -1  # overlap
     assert "overlap" in w.last_error()
+

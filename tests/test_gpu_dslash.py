@@ -77,13 +77,18 @@ def test_even_odd(w, dims, prec, link):
             got = gu.half_to_canon(w, half, dims, prec, p)
             want = oracle.dslash_eo(U, psi, dims, p, phases, dagger=dag)
             gu.assert_close(got[sel], want[sel], gu.TOL[prec], "hop p=%d dag=%d" % (p, dag))
-            # Schur complement on parity p
-            w.wilson_dslash_eo(G, w.parity_block(P, dims, prec, p), half, dims, kappa, p,
+            # Schur complement on parity p: out is a full field whose other
+            # parity block receives the intermediate D_{1-p,p} in
+            full = w.empty_spinor(dims, prec, 2)
+            w.wilson_dslash_eo(G, w.parity_block(P, dims, prec, p), full, dims, kappa, p,
                                phases, f)
-            got = gu.half_to_canon(w, half, dims, prec, p)
+            got = gu.half_to_canon(w, w.parity_block(full, dims, prec, p), dims, prec, p)
             psi_p = psi * sel[:, None, None]
             want = oracle.schur(U, psi_p, dims, kappa, p, phases, dagger=dag)
             gu.assert_close(got[sel], want[sel], gu.TOL[prec], "schur p=%d dag=%d" % (p, dag))
+            mid = gu.half_to_canon(w, w.parity_block(full, dims, prec, 1 - p), dims, prec, 1 - p)
+            want = oracle.dslash_eo(U, psi_p, dims, 1 - p, phases, dagger=dag)
+            gu.assert_close(mid[~sel], want[~sel], gu.TOL[prec], "schur intermediate p=%d" % p)
 
 
 def test_pack_roundtrip(w):
@@ -195,6 +200,8 @@ def test_invalid_arguments_enqueue_nothing(w):
         w.wilson_dslash(G, P, w.empty_spinor(dims), (4, 4, 4, 5), 0.1)   # odd extent
     with pytest.raises(w.WilsonError):
         w.wilson_dslash_eo(G, P, w.empty_spinor(dims), dims, 0.1, 2)     # bad parity
+    with pytest.raises(w.WilsonError):   # Schur mode: in inside out's scratch block
+        w.wilson_dslash_eo(G, w.parity_block(P, dims, 0, 1), P, dims, 0.1, 0)
 
 
 @pytest.fixture(scope="module")

@@ -124,3 +124,28 @@ def test_problem_errors(w):
         w.solve_cg_problems(probs)
     with pytest.raises(w.WilsonError):
         w.solve_cg_problems(build(w, specs, 0), flags=w.F32)
+
+
+def test_tuned_shared_gauge_shape_never_reaches_per_problem_gauges(w):
+    """A shared-gauge batch at 16^3 x 32 (time slices of whole site blocks, so
+    its launches are autotuned and may settle on several RHS per thread) runs
+    first; then 4 problems of the same size, each with its own gauge field, are
+    solved together. Each must use its own links: every solution meets the
+    oracle's residual with that problem's field, and equals its solo solve."""
+    dims = (16, 16, 16, 32)
+    U0 = synth.gauge_haar(dims, 50)
+    G0 = w.pack_gauge(U0, dims)
+    n = 4
+    B = w.empty_batch(dims, n)
+    for r in range(n):
+        w.batch_field(B, dims, 0, r).copy_(w.pack_spinor(synth.gaussian_spinor(dims, 60 + r), dims))
+    X = w.empty_batch(dims, n)
+    code, _ = w.solve_cg_batch(G0, B, X, n, dims, 0.12, flags=w.EO)
+    assert code == 0
+    assert "gauges=shared" in w.tuning_report()
+    specs = [dict(dims=dims, kappa=0.11 + 0.005 * i, U=synth.gauge_haar(dims, 70 + i),
+                  b=synth.gaussian_spinor(dims, 80 + i)) for i in range(n)]
+    probs = build(w, specs, w.EO)
+    code, stats = w.solve_cg_problems(probs, flags=w.EO)
+    assert code == 0, stats
+    check_against_solo(w, specs, probs, stats, w.EO)

@@ -153,19 +153,52 @@ def test_failure_statuses(w, cfg1):
     assert not gu.to_np(w.unpack_spinor(X, dims)).any()
 
 
-@pytest.mark.parametrize("flags", [0x20 | 0x40, 0x20 | 0x40 | 0x2, 0x0],
-                         ids=["eo-mixed-f32", "eo-mixed-f16", "full-f64"])
-def test_bicgstab_past_critical_kappa_keeps_best_iterate(w, flags):
-    """16^3 x 32, kappa = 0.15 (past the crossing of Re lambda(M) = 0 for these
-    fields): BiCGStab may stagnate or break down (a Krylov scalar vanishes),
-    but the returned x is never worse than the start (x = 0, residual 1) and
-    the reported residual is the oracle's."""
-    dims, kappa = (16, 16, 16, 32), 0.15
-    U = synth.gauge_smooth(dims, 0.3, 0)
-    b = synth.gaussian_spinor(dims, 1)
+@pytest.fixture(scope="module")
+def cfg2():
+    """16^3 x 32, exp(i 0.3 H) links (seed 0), kappa = 0.15, Gaussian source
+    (seed 1): the BiCGStab configuration."""
+    dims = (16, 16, 16, 32)
+    return dims, 0.15, synth.gauge_smooth(dims, 0.3, 0), synth.gaussian_spinor(dims, 1)
+
+
+@pytest.mark.parametrize("flags", [0x20, 0x20 | 0x4, 0x20 | 0x40, 0x20 | 0x40 | 0x2,
+                                   0x20 | 0x40 | 0x4],
+                         ids=["eo-f64", "eo-f64-link12", "eo-mixed-f32", "eo-mixed-f16",
+                              "eo-mixed-f32-link12"])
+def test_config2_bicgstab_converges(w, cfg2, flags):
+    """BiCGStab on the even-odd system to 1e-10 at 16^3 x 32, kappa = 0.15 (past
+    the crossing of Re lambda(M) = 0 for these fields, where BiCGStab needs
+    restarts): the FP64 solve, and the mixed ones (FP32 or FP16-storage
+    reliable-update sequences, continued in FP64 if they stall), all reach the
+    oracle's true residual 1e-10. The iteration split is printed."""
+    dims, kappa, U, b = cfg2
+    G = w.pack_gauge(U, dims, flags & 0x4)
+    X = w.empty_spinor(dims)
+    st = w.solve_bicgstab(G, w.pack_spinor(b, dims), X, dims, kappa, maxiter=60000,
+                          flags=flags)
+    print("bicgstab %s: %s, %d iterations (%d in FP64), %d restarts, %d reliable updates, "
+          "%.3f s, true residual %.2e" % (_name(("bicgstab", flags)), st["status_name"],
+                                          st["iterations"], st["fp64_iterations"],
+                                          st["restarts"], st["reliable_updates"],
+                                          st["seconds"], st["true_res"]))
+    assert st["status"] == w.OK, st
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    res = oracle.true_residual(U, b, x, dims, kappa)
+    assert res <= 1e-10, (st, res)
+    assert abs(res - st["true_res"]) <= 1e-12, (st, res)
+    if not flags & 0x40:
+        assert st["fp64_iterations"] == st["iterations"]
+
+
+def test_full_lattice_bicgstab_past_critical_kappa_keeps_best_iterate(w, cfg2):
+    """The same system without even-odd preconditioning: full-lattice BiCGStab
+    may stagnate or break down there (a Krylov scalar vanishes), but the
+    returned x is never worse than the start (x = 0, residual 1) and the
+    reported residual is the oracle's."""
+    dims, kappa, U, b = cfg2
     G = w.pack_gauge(U, dims)
     X = w.empty_spinor(dims)
-    st = w.solve_bicgstab(G, w.pack_spinor(b, dims), X, dims, kappa, maxiter=20000, flags=flags)
+    st = w.solve_bicgstab(G, w.pack_spinor(b, dims), X, dims, kappa, maxiter=20000, flags=0)
     assert st["status"] in (w.OK, w.NOCONV, w.STAGNATED, w.BREAKDOWN), st
     x = gu.to_np(w.unpack_spinor(X, dims))
     res = oracle.true_residual(U, b, x, dims, kappa)
