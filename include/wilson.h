@@ -250,6 +250,26 @@ int solve_bicgstab_tm(const void *gauge, const void *b, void *x,
                       uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): solve_cg without a workspace argument.
+ * The solver's scratch is a static device array of 64 MiB (64 << 20 bytes)
+ * that the library holds on every GPU it runs on until the process ends;
+ * this call allocates nothing (no hipMalloc/hipFree, no pinned host memory,
+ * no autotuning events; status words are read through plain host memory).
+ * Arguments, flags, layouts, results and return codes are those of
+ * solve_cg, whose kernels it shares, so a solution has the bits of the same
+ * solve_cg call. Returns WL_EWORKSPACE (nothing done) when
+ * wl_workspace_bytes(dims, flags, 1) exceeds 64 MiB -- e.g. FP64 solves up to
+ * about 32k sites (8^3 x 16 fits, 12^3 x 24 does not) -- and WL_EINVAL with
+ * WL_GRAPH (graph instantiation allocates). Every call on one GPU uses that
+ * GPU's one array and leaves its contents behind; the solver initialises
+ * everything it reads, but calls that overlap in time on one GPU (from
+ * several host threads) race on the array and must not be made. Blocks
+ * until the solve is complete. */
+int solve_cg_noalloc(const void *gauge, const void *b, void *x, const int32_t dims[4],
+                     double kappa, const double phases[8], double tol, int32_t maxiter,
+                     uint32_t flags, wl_solve_stats *stats, void *stream);
+
 /* Batched operator: `in` and `out` each hold nrhs packed full spinors one
  * after another (stride wl_spinor_bytes(dims, flags, 2)); the modes are those
  * of wilson_dslash. All nrhs fields share the gauge field, whose links are

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "wl_host.h"
@@ -422,16 +423,71 @@ int solve_cg_batch(const void *gauge, const void *b, void *x, int32_t nrhs,
     return st;
 }
 
+// Scratch of the allocation-free solve entry point: one array per GPU the
+// library runs on, held until the process ends. Host code never uses the
+// array's name as an address: scratch_address() looks up each device's copy
+// once (with that device current) and the solver is handed that pointer.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void **out, std::string *why) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *why = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return WL_EHIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *why = "device index out of range for the static scratch table";
+        return WL_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return WL_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return WL_OK;
+}
+}  // namespace
+
 static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
                         const int32_t dims[4], double kappa, const double phases[8], double tol,
                         int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
-                        wl_solve_stats *stats, void *stream, double mu = 0.0) {
+                        wl_solve_stats *stats, void *stream, bool static_scratch = false,
+                        double mu = 0.0) {
     SolveIn in{};
     if (!std::isfinite(mu)) return fail(WL_EINVAL, "mu is not finite");
     in.mu = mu;
     std::string why;
     if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
         return fail(WL_EINVAL, why);
+    if (static_scratch) {
+        if (flags & WL_GRAPH)
+            return fail(WL_EINVAL, "solve_cg_noalloc: WL_GRAPH instantiates graphs, which "
+                                   "allocates; use solve_cg for graph replay");
+        const size_t need = workspace_bytes(in.g, flags);
+        if (need > kStaticScratchBytes)
+            return fail(WL_EWORKSPACE,
+                        "solve_cg_noalloc: this solve needs " + std::to_string(need) +
+                            " bytes of scratch, more than the static scratch of " +
+                            std::to_string(kStaticScratchBytes) +
+                            " bytes; use solve_cg with a workspace");
+        const int e = scratch_address(&work, &why);
+        if (e != WL_OK) return fail(e, why);
+        work_bytes = kStaticScratchBytes;
+        in.no_alloc = true;
+    }
     if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
     const uint32_t inner = flags & WL_PREC_MASK;
     if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
@@ -456,7 +512,13 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     in.flags = flags;
     in.work = work;
     in.s = static_cast<hipStream_t>(stream);
-    const int st = run_solver(bicg, in, stats, &why);
+    int st;
+    if (in.no_alloc) {
+        const TuningSuspended no_tuning;   // tuning would create events
+        st = run_solver(bicg, in, stats, &why);
+    } else {
+        st = run_solver(bicg, in, stats, &why);
+    }
     if (st != WL_OK) {
         if (why.empty()) {
             static const char *names[] = {"ok", "not converged within maxiter",
@@ -480,7 +542,7 @@ int solve_cg_tm(const void *gauge, const void *b, void *x, const int32_t dims[4]
                 double mu, const double phases[8], double tol, int32_t maxiter, uint32_t flags,
                 void *work, size_t work_bytes, wl_solve_stats *stats, void *stream) {
     return solve_common(false, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
-                        work_bytes, stats, stream, mu);
+                        work_bytes, stats, stream, false, mu);
 }
 
 int solve_bicgstab_tm(const void *gauge, const void *b, void *x, const int32_t dims[4],
@@ -488,7 +550,14 @@ int solve_bicgstab_tm(const void *gauge, const void *b, void *x, const int32_t d
                       int32_t maxiter, uint32_t flags, void *work, size_t work_bytes,
                       wl_solve_stats *stats, void *stream) {
     return solve_common(true, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work,
-                        work_bytes, stats, stream, mu);
+                        work_bytes, stats, stream, false, mu);
+}
+
+int solve_cg_noalloc(const void *gauge, const void *b, void *x, const int32_t dims[4],
+                     double kappa, const double phases[8], double tol, int32_t maxiter,
+                     uint32_t flags, wl_solve_stats *stats, void *stream) {
+    return solve_common(false, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, nullptr, 0,
+                        stats, stream, true);
 }
 
 int solve_bicgstab(const void *gauge, const void *b, void *x, const int32_t dims[4],

@@ -1,6 +1,7 @@
 // wl_dslash.hip -- launch dispatch of the hopping term and the autotuner's
 // shape record (the kernels are in wl_hop.h).
 #include "wl_hop.h"
+#include "wl_host.h"
 
 namespace wl {
 
@@ -59,7 +60,15 @@ std::string tune_key(const Geom &g, int prec, bool link12, bool dag, bool xpay, 
     return k;
 }
 
+namespace {
+thread_local int t_tuning_suspended = 0;
+}
+
+TuningSuspended::TuningSuspended() { ++t_tuning_suspended; }
+TuningSuspended::~TuningSuspended() { --t_tuning_suspended; }
+
 bool tuning_enabled() {
+    if (t_tuning_suspended > 0) return false;
     const char *v = std::getenv("WL_TUNE");
     return !(v && v[0] == '0');
 }

@@ -7,6 +7,15 @@
 
 namespace wl {
 
+// While a thread holds one of these, launches on it use recorded or default
+// launch shapes and never time candidates (no events are created).
+struct TuningSuspended {
+    TuningSuspended();
+    ~TuningSuspended();
+    TuningSuspended(const TuningSuspended &) = delete;
+    TuningSuspended &operator=(const TuningSuspended &) = delete;
+};
+
 // ---- solvers ---------------------------------------------------------------
 size_t workspace_bytes(const Geom &g, uint32_t flags);
 
@@ -28,6 +37,7 @@ struct SolveIn {
     const double *kappas = nullptr;
     const void *const *gauges_host = nullptr;   // the gtab entries, readable on the host
     bool own_stream = false;   // `s` belongs to the library: capture on it directly
+    bool no_alloc = false;     // read status into plain host memory, no tuning runs
 };
 
 int run_solver(bool bicg, const SolveIn &in, wl_solve_stats *st, std::string *why);

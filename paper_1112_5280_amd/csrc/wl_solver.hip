@@ -105,7 +105,21 @@ struct PinnedScalars {
     }
 };
 
+// A solve that may allocate nothing reads its status through plain host
+// memory instead (pageable copies are slower, but need no allocation).
+thread_local bool t_pageable_status = false;
+
+struct PageableStatus {
+    bool prev;
+    explicit PageableStatus(bool on) : prev(t_pageable_status) { t_pageable_status = prev || on; }
+    ~PageableStatus() { t_pageable_status = prev; }
+};
+
 static Scalars *host_scalars() {
+    if (t_pageable_status) {
+        thread_local Scalars plain[kMaxBatch];
+        return plain;
+    }
     thread_local PinnedScalars buf;
     if (!buf.p)
         check(hipHostMalloc(reinterpret_cast<void **>(&buf.p), sizeof(Scalars) * kMaxBatch,
@@ -830,6 +844,7 @@ static bool graph_setup(SolveIn &in, std::string *why) {
 int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *why) {
     const auto t0 = std::chrono::steady_clock::now();
     SolveIn in = in0;
+    const PageableStatus pageable(in.no_alloc);
     if (!graph_setup(in, why)) return WL_EHIP;
     const bool graph = in.flags & WL_GRAPH;
     const Geom &g = in.g;

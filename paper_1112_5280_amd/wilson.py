@@ -48,7 +48,7 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_problems_workspace_bytes", "solve_cg_problems",
            "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
            "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy",
-           "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
+           "solve_cg_noalloc", "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
            "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators")
 
 
@@ -123,6 +123,9 @@ def _load():
     lib.wl_meson_workspace_bytes.restype = SZ
     lib.wl_meson_correlators.argtypes = [P, P, I32, P, P, SZ, P]
     lib.wl_meson_correlators.restype = ctypes.c_int
+    lib.solve_cg_noalloc.argtypes = [P, P, P, P, D, P, D, I32, U32,
+                                     ctypes.POINTER(SolveStats), P]
+    lib.solve_cg_noalloc.restype = ctypes.c_int
     lib.wilson_dslash_batch.argtypes = [P, P, P, I32, P, D, P, U32, P]
     lib.wilson_dslash_batch.restype = ctypes.c_int
     lib.solve_cg_batch.argtypes = [P, P, P, I32, P, D, P, D, I32, U32, P, SZ,
@@ -318,6 +321,22 @@ def solve_bicgstab(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
     """BiCGStab solve of M x = b (packed FP64 b, x); returns the stats dict."""
     return _solve(lib.solve_bicgstab, "solve_bicgstab", gauge, b, x, dims, kappa, phases,
                   tol, maxiter, flags, work, stream)
+
+
+def solve_cg_noalloc(gauge, b, x, dims, kappa, phases=ANTIPERIODIC_T, tol=1e-10,
+                     maxiter=100000, flags=F64, stream=None):
+    """solve_cg with the library's static scratch instead of a workspace: the
+    call allocates nothing (lattices whose workspace fits in 64 MiB)."""
+    st = SolveStats()
+    code = lib.solve_cg_noalloc(_ptr(gauge), _ptr(b), _ptr(x), _dims(dims), float(kappa),
+                                _phases(phases), float(tol), int(maxiter), flags,
+                                ctypes.byref(st), _stream(stream))
+    _check(code, "solve_cg_noalloc")
+    d = st.as_dict()
+    d["status_name"] = STATUS_NAMES.get(code, "?")
+    if code != OK:
+        d["message"] = last_error()
+    return d
 
 
 def wilson_dslash_tm(gauge, inp, out, dims, kappa, mu, phases=ANTIPERIODIC_T, flags=F64,

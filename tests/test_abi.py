@@ -162,3 +162,22 @@ def test_stream_copy_checks(w):
     assert lib.wl_stream_copy(_p(4096), _p(4096 + 32), 64, None) == -1  # overlap
     assert "overlap" in w.last_error()
 
+
+def test_noalloc_solve_rejects_before_touching_the_gpu(w):
+    """solve_cg_noalloc refuses, with nothing done, a lattice whose workspace
+    exceeds its 64 MiB static scratch, and graph replay (which allocates)."""
+    ph = (ctypes.c_double * 8)(1, 0, 1, 0, 1, 0, -1, 0)
+    st = w.SolveStats()
+    big = w._dims((16, 16, 16, 32))       # FP64 workspace ~ 230 MB
+    assert w.workspace_bytes((16, 16, 16, 32), 0) > (64 << 20)
+    assert w.lib.solve_cg_noalloc(_p(8), _p(16), _p(32), big, 0.1, ph, 1e-10, 10, 0,
+                                  ctypes.byref(st), None) == w.EWORKSPACE
+    assert b"static scratch" in w.lib.wl_last_error()
+    small = w._dims((4, 4, 4, 4))
+    assert w.lib.solve_cg_noalloc(_p(8), _p(16), _p(32), small, 0.1, ph, 1e-10, 10, w.GRAPH,
+                                  ctypes.byref(st), None) == w.EINVAL
+    assert w.lib.solve_cg_noalloc(_p(8), _p(16), _p(32), w._dims((4, 4, 4, 5)), 0.1, ph,
+                                  1e-10, 10, 0, ctypes.byref(st), None) == w.EINVAL
+    # the small configurations of the uneven batch fit
+    for d in ((4, 4, 4, 4), (8, 8, 8, 8), (8, 8, 8, 16)):
+        assert w.workspace_bytes(d, w.EO | w.MIXED) <= (64 << 20)
