@@ -44,6 +44,9 @@ PINS = {
     "mop_tm/cgnr_tm": "free-field eigenvalues 1 - 2k sum cos p +- 2ik sqrt(mu^2 + "
                       "sum sin^2 p); g5 M(mu) g5 = M(-mu)^dag; mu = 0 is M; dense "
                       "2x4x2x4 with the twist; LAPACK solve",
+    "philox/kp_samples/heatbath": "Philox4x32-10 known-answer vectors; the Kennedy-"
+                                  "Pendleton density (mean I_2/I_1, KS test); SU(3) kept; "
+                                  "strong-coupling beta/18 and weak-coupling 1 - 2/beta",
     "meson": "pion channel -sum |S|^2; completeness of the 16 Gammas "
              "(sum_n Gamma_n^2 C_n = -4 sum |Tr_spin S|^2); gauge invariance; time shift",
     "cgnr_eo": "LAPACK dense solve on 4^4 and 2x4x2x4; the odd rows of M x = b "
@@ -126,6 +129,9 @@ class Oracle:
         lib.orc_lanczos_mdm.argtypes = [P, P, P, P, D, I, P, P]
         lib.orc_lanczos_mdm.restype = I
         lib.orc_meson.argtypes = [P, P, I, P]
+        lib.orc_philox.argtypes = [P, P, P]
+        lib.orc_kp_samples.argtypes = [D, I, ctypes.c_uint32, P]
+        lib.orc_heatbath.argtypes = [P, P, D, I, ctypes.c_uint32, ctypes.c_uint32]
         lib.orc_plaquette.argtypes = [P, P]
         lib.orc_plaquette.restype = D
         for fn in (lib.orc_cgnr, lib.orc_cgnr_eo, lib.orc_bicgstab):
@@ -273,6 +279,31 @@ class Oracle:
         self.lib.orc_meson(_ptr(pr), _ptr(d), int(t0), _ptr(out))
         return out
 
+    def philox(self, ctr, key):
+        """Philox4x32-10 of a 4-word counter and a 2-word key (four words)."""
+        c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+        k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+        o = np.zeros(4, dtype=np.uint32)
+        self.lib.orc_philox(_ptr(c), _ptr(k), _ptr(o))
+        return [int(v) for v in o]
+
+    def kp_samples(self, alpha, n, seed=0):
+        """n Kennedy-Pendleton draws of x0 (density ~ sqrt(1 - x0^2) exp(alpha x0))."""
+        out = np.zeros(int(n))
+        self.lib.orc_kp_samples(float(alpha), int(n), int(seed) & 0xffffffff, _ptr(out))
+        return out
+
+    def heatbath(self, U, dims, beta, nsweeps, sweep0=0, seed=0):
+        """nsweeps SU(3) heat-bath sweeps (Cabibbo-Marinari, Kennedy-Pendleton,
+        Philox4x32-10 counters) in place on U [V, 4, 3, 3] (C-contiguous complex128)."""
+        d = _dims(dims)
+        if not (isinstance(U, np.ndarray) and U.dtype == np.complex128 and
+                U.flags["C_CONTIGUOUS"] and U.shape == (_vol(d), 4, 3, 3)):
+            raise ValueError("U must be a C-contiguous complex128 array [V, 4, 3, 3]")
+        self.lib.orc_heatbath(_ptr(U), _ptr(d), float(beta), int(nsweeps),
+                              int(sweep0) & 0xffffffff, int(seed) & 0xffffffff)
+        return U
+
     def plaquette(self, U, dims) -> float:
         d = _dims(dims)
         U = _c128(U, (_vol(d), 4, 3, 3))
@@ -366,7 +397,8 @@ def _forward(name):
 
 for _name in ("set_threads", "max_threads", "gamma", "dslash", "mop",
               "mop_sites", "dslash_sites", "dslash_eo", "schur", "plaquette",
-              "cgnr", "cgnr_eo", "bicgstab", "mop_tm", "schur_tm", "cgnr_tm", "meson", "true_residual_tm", "true_residual", "singular_extremes"):
+              "cgnr", "cgnr_eo", "bicgstab", "mop_tm", "schur_tm", "cgnr_tm", "meson", "philox", "kp_samples",
+              "heatbath", "true_residual_tm", "true_residual", "singular_extremes"):
     globals()[_name] = _forward(_name)
 
 

@@ -483,6 +483,212 @@ void orc_meson(const cplx *props, const int L[4], int t0, cplx *corr)
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Pure-gauge update (paper Sec. 3: the heatbath that generates the gauge    */
+/* configurations): Wilson plaquette action                                  */
+/*   S = beta sum_P (1 - Re Tr U_P / 3),                                     */
+/* Cabibbo-Marinari heatbath over the three SU(2) subgroups of each link,   */
+/* each drawn with the Kennedy-Pendleton algorithm.                          */
+/* ------------------------------------------------------------------------ */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter c[4], key k[2].
+   Ten rounds of two 32x32 -> 64 multiplications with the Weyl-sequence key
+   schedule between rounds. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* four uniforms in (0, 1): (x + 1/2) / 2^32 of the four Philox words */
+static void uniforms4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                      const uint32_t key[2], double u[4])
+{
+    uint32_t ctr[4] = {a, b, c, d}, o[4];
+    orc_philox(ctr, key, o);
+    for (int i = 0; i < 4; ++i) u[i] = ((double)o[i] + 0.5) / 4294967296.0;
+}
+
+/* Kennedy-Pendleton: x0 in [-1, 1] with density ~ sqrt(1 - x0^2) exp(alpha x0).
+   Candidate lambda^2 = -(ln r1 + cos^2(2 pi r2) ln r3) / (2 alpha), accepted
+   when r4^2 <= 1 - lambda^2; x0 = 1 - 2 lambda^2. Attempt n draws its four
+   uniforms from the counter (site, tag + 16 n, sweep, 0). Returns 0 and sets
+   *x0 when accepted within HB_MAX_TRIES attempts, else -1. */
+#define HB_MAX_TRIES 64
+static int kp_draw(double alpha, uint32_t site, uint32_t tag, uint32_t sweep,
+                   const uint32_t key[2], double *x0)
+{
+    for (uint32_t n = 0; n < HB_MAX_TRIES; ++n) {
+        double u[4];
+        uniforms4(site, tag + 16u * n, sweep, 0u, key, u);
+        double c = cos(2.0 * M_PI * u[1]);
+        double l2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
+        if (u[3] * u[3] <= 1.0 - l2) {
+            *x0 = 1.0 - 2.0 * l2;
+            return 0;
+        }
+    }
+    return -1;
+}
+
+/* Samples of the Kennedy-Pendleton draw for one alpha (to pin its density). */
+void orc_kp_samples(double alpha, int n, uint32_t seed, double *out)
+{
+    uint32_t key[2] = {seed, 0x6b707070u};
+    for (int i = 0; i < n; ++i) {
+        double x0 = 2.0;
+        if (kp_draw(alpha, (uint32_t)i, 0u, 0u, key, &x0) != 0) x0 = 2.0;
+        out[i] = x0;
+    }
+}
+
+static void su3_mul(const cplx *a, const cplx *b, cplx *c)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 3; ++k) s += a[i * 3 + k] * b[k * 3 + j];
+            c[i * 3 + j] = s;
+        }
+}
+
+static void su3_mul_dag(const cplx *a, const cplx *b, cplx *c) /* a b^dag */
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 3; ++k) s += a[i * 3 + k] * conj(b[j * 3 + k]);
+            c[i * 3 + j] = s;
+        }
+}
+
+static void su3_dag_mul(const cplx *a, const cplx *b, cplx *c) /* a^dag b */
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = 0;
+            for (int k = 0; k < 3; ++k) s += conj(a[k * 3 + i]) * b[k * 3 + j];
+            c[i * 3 + j] = s;
+        }
+}
+
+static long shift(const int L[4], const int c[4], int mu, int d)
+{
+    int e[4] = {c[0], c[1], c[2], c[3]};
+    e[mu] = (e[mu] + d + L[mu]) % L[mu];
+    return index_of(L, e);
+}
+
+/* Sum of the six staples of U_mu(x), so that the action's part with this
+   link is -(beta / 3) Re Tr(U_mu(x) A):
+     A = sum_{nu != mu} U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+                      + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)      */
+static void staple_sum(const cplx *U, const int L[4], long s, int mu, cplx A[9])
+{
+    int c[4];
+    coords_of(L, s, c);
+    memset(A, 0, sizeof(cplx) * 9);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        long xpmu = shift(L, c, mu, 1), xpnu = shift(L, c, nu, 1), xmnu = shift(L, c, nu, -1);
+        int cm[4];
+        coords_of(L, xmnu, cm);
+        long xpmu_mnu = shift(L, cm, mu, 1);
+        cplx t1[9], t2[9], m[9];
+        /* upper: U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag */
+        su3_mul_dag(U + (xpmu * 4 + nu) * 9, U + (xpnu * 4 + mu) * 9, t1);
+        su3_mul_dag(t1, U + (s * 4 + nu) * 9, t2);
+        for (int k = 0; k < 9; ++k) A[k] += t2[k];
+        /* lower: U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+                = (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu) */
+        su3_mul(U + (xmnu * 4 + mu) * 9, U + (xpmu_mnu * 4 + nu) * 9, m);
+        su3_dag_mul(m, U + (xmnu * 4 + nu) * 9, t2);
+        for (int k = 0; k < 9; ++k) A[k] += t2[k];
+    }
+}
+
+/* One heatbath update of U_mu(x) (Cabibbo-Marinari): for the SU(2)
+   subgroups on rows/columns (0,1), (1,2), (0,2) in turn, with W = U A and w
+   its 2 x 2 block, Re Tr(r w) = 2 (r . b) for an SU(2) element
+   r = [[r0 + i r3, r2 + i r1], [-r2 + i r1, r0 - i r3]] and
+     b = (Re(w00 + w11), -Im(w01 + w10), Re(w10 - w01), -Im(w00 - w11)) / 2.
+   With k = |b| and V the SU(2) element of b / k, r = X V where X has the
+   density exp(alpha X0) on SU(2), alpha = 2 beta k / 3: X0 from the
+   Kennedy-Pendleton draw, (X1, X2, X3) uniform on the sphere of radius
+   sqrt(1 - X0^2) (cos theta = 2 u - 1, phi = 2 pi v from the counter
+   (site, tag, sweep, 1)). Then U <- R U, R = r on rows (i, j). A subgroup
+   whose draw is not accepted within HB_MAX_TRIES attempts is left as it is. */
+static void hb_link(cplx *U, const int L[4], long s, int mu, double beta,
+                    uint32_t sweep, const uint32_t key[2])
+{
+    static const int SUB[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+    cplx A[9];
+    staple_sum(U, L, s, mu, A);
+    cplx *u = U + (s * 4 + mu) * 9;
+    for (int g = 0; g < 3; ++g) {
+        int i = SUB[g][0], j = SUB[g][1];
+        cplx W[9];
+        su3_mul(u, A, W);
+        cplx w00 = W[i * 3 + i], w01 = W[i * 3 + j], w10 = W[j * 3 + i], w11 = W[j * 3 + j];
+        double b0 = creal(w00 + w11) / 2, b1 = -cimag(w01 + w10) / 2;
+        double b2 = creal(w10 - w01) / 2, b3 = -cimag(w00 - w11) / 2;
+        double k = sqrt(b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3);
+        if (!(k > 0.0)) continue;
+        uint32_t tag = (uint32_t)mu | ((uint32_t)g << 2);
+        double x0;
+        if (kp_draw(2.0 * beta * k / 3.0, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;
+        double d[4];
+        uniforms4((uint32_t)s, tag, sweep, 1u, key, d);
+        double ct = 2.0 * d[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        double ph = 2.0 * M_PI * d[1], rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
+        double x1 = rad * st * cos(ph), x2 = rad * st * sin(ph), x3 = rad * ct;
+        double v0 = b0 / k, v1 = b1 / k, v2 = b2 / k, v3 = b3 / k;
+        cplx X[4] = {x0 + I * x3, x2 + I * x1, -x2 + I * x1, x0 - I * x3};
+        cplx Vm[4] = {v0 + I * v3, v2 + I * v1, -v2 + I * v1, v0 - I * v3};
+        cplx r[4] = {X[0] * Vm[0] + X[1] * Vm[2], X[0] * Vm[1] + X[1] * Vm[3],
+                     X[2] * Vm[0] + X[3] * Vm[2], X[2] * Vm[1] + X[3] * Vm[3]};
+        for (int col = 0; col < 3; ++col) {
+            cplx ui = u[i * 3 + col], uj = u[j * 3 + col];
+            u[i * 3 + col] = r[0] * ui + r[1] * uj;
+            u[j * 3 + col] = r[2] * ui + r[3] * uj;
+        }
+    }
+}
+
+/* nsweeps heatbath sweeps at coupling beta, sweep numbers sweep0, sweep0+1, ...
+   (part of every random counter); within a sweep the links of direction mu
+   on the even, then the odd sites, for mu = 0..3 (links of one direction and
+   parity do not enter each other's staples, so their order is free). */
+void orc_heatbath(cplx *U, const int L[4], double beta, int nsweeps, uint32_t sweep0,
+                  uint32_t seed)
+{
+    long V = volume4(L);
+    uint32_t key[2] = {seed, 0x68656174u};
+    for (int n = 0; n < nsweeps; ++n)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+#pragma omp parallel for schedule(static)
+                for (long s = 0; s < V; ++s) {
+                    int c[4];
+                    coords_of(L, s, c);
+                    if (parity_of(c) == par) hb_link(U, L, s, mu, beta, sweep0 + (uint32_t)n, key);
+                }
+            }
+}
+
 /* Mean plaquette: average over sites and the 6 planes of Re tr(U_mu nu)/3. */
 double orc_plaquette(const cplx *U, const int L[4])
 {

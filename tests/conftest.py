@@ -13,3 +13,10 @@ def pytest_configure(config):
         "markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line(
         "markers", "slow: CPU test that takes more than a few seconds")
+
+
+if os.environ.get("PYTEST_XDIST_WORKER"):
+    # parallel workers share the CPUs: one BLAS thread each, else the dense
+    # LAPACK pins oversubscribe the cores and run many times slower
+    from threadpoolctl import threadpool_limits
+    _BLAS_LIMIT = threadpool_limits(1)

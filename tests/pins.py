@@ -465,6 +465,68 @@ def pin_meson_gauge_invariance(orc, dims=(2, 2, 4, 4)):
     assert rel(orc.meson(props2, dims), orc.meson(props, dims)) < 1e-13
 
 
+def pin_philox_known_answers(orc):
+    """Philox4x32-10 reproduces the known-answer vectors published with the
+    generator (Random123): zero counter and key, all-ones, and the digits of
+    pi."""
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+             ((0xffffffff,) * 4, (0xffffffff, 0xffffffff),
+              (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+             ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+              (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for ctr, key, want in cases:
+        assert tuple(orc.philox(ctr, key)) == want, (ctr, key)
+
+
+def pin_kp_density(orc):
+    """The Kennedy-Pendleton draw samples x0 with density proportional to
+    sqrt(1 - x0^2) exp(alpha x0) on [-1, 1]: its mean is I_2(alpha)/I_1(alpha),
+    and a Kolmogorov-Smirnov test against the numerically integrated
+    distribution function accepts it."""
+    from scipy import integrate, special, stats
+    n = 200000
+    for alpha in (0.4, 2.5, 12.0):
+        x = orc.kp_samples(alpha, n, seed=5)
+        assert (np.abs(x) <= 1).all()
+        mean = special.iv(2, alpha) / special.iv(1, alpha)
+        z = integrate.quad(lambda t: np.sqrt(1 - t * t) * np.exp(alpha * t), -1, 1)[0]
+        m2 = integrate.quad(lambda t: t * t * np.sqrt(1 - t * t) * np.exp(alpha * t), -1, 1)[0] / z
+        assert abs(x.mean() - mean) < 5 * np.sqrt((m2 - mean ** 2) / n), (alpha, x.mean(), mean)
+        grid = np.linspace(-1, 1, 200001)
+        dens = np.sqrt(1 - grid * grid) * np.exp(alpha * grid)
+        cum = np.concatenate([[0.0], np.cumsum((dens[1:] + dens[:-1]) / 2 * np.diff(grid))])
+        cum /= cum[-1]
+        assert stats.kstest(x[:20000], lambda q: np.interp(q, grid, cum)).pvalue > 1e-4, alpha
+
+
+def pin_heatbath_unitary_and_strong_coupling(orc, dims=(4, 4, 4, 4)):
+    """Heat-bath sweeps keep every link in SU(3); at strong coupling the mean
+    plaquette is beta/18 to leading order (beta = 0.3: corrections are far
+    below the statistical error), and at weak coupling it is 1 - 2/beta to
+    leading order (equipartition over the 8 gauge degrees of freedom of each
+    of the 3 non-gauge link directions per site, beta = 80)."""
+    V = int(np.prod(dims))
+    U = synth.gauge_haar(dims, 71)
+    orc.heatbath(U, dims, 0.3, 20, sweep0=0, seed=9)
+    m = U.reshape(-1, 3, 3)
+    assert np.abs(m @ np.conj(np.swapaxes(m, 1, 2)) - np.eye(3)).max() < 1e-13
+    assert np.abs(np.linalg.det(m) - 1).max() < 1e-13
+    ps = []
+    for k in range(60):
+        orc.heatbath(U, dims, 0.3, 1, sweep0=20 + k, seed=9)
+        ps.append(orc.plaquette(U, dims))
+    p = float(np.mean(ps))
+    err = float(np.std(ps)) / np.sqrt(len(ps))
+    assert abs(p - 0.3 / 18) < 5 * err + 2e-4, (p, err)
+    U = synth.gauge_unit(dims)
+    orc.heatbath(U, dims, 80.0, 30, sweep0=0, seed=10)
+    ps = []
+    for k in range(30):
+        orc.heatbath(U, dims, 80.0, 1, sweep0=30 + k, seed=10)
+        ps.append(orc.plaquette(U, dims))
+    assert abs(np.mean(ps) - (1 - 2 / 80.0)) < 2e-3, np.mean(ps)
+
+
 def pin_plaquette(orc, dims=(4, 4, 2, 4)):
     """Unit links give plaquette 1; the plaquette is gauge invariant."""
     assert abs(orc.plaquette(synth.gauge_unit(dims), dims) - 1.0) < 1e-15
@@ -515,6 +577,7 @@ ALL_PINS = [
     pin_neumann, pin_free_field_solve, pin_eo_solve_odd_rows, pin_plaquette,
     pin_tm_free_field_spectrum, pin_tm_dense_and_adjoint, pin_tm_solve_lapack,
     pin_tm_schur_block_elimination, pin_meson_pion_and_completeness,
-    pin_meson_gauge_invariance,
+    pin_meson_gauge_invariance, pin_philox_known_answers, pin_kp_density,
+    pin_heatbath_unitary_and_strong_coupling,
     pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]

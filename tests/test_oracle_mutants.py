@@ -83,6 +83,15 @@ MUTANTS = [
      "tr_ += S[j][i] * ASB[j][i];"),
     ("meson: time not counted from t0", "int tr = ((c[3] - t0) % Lt + Lt) % Lt;",
      "int tr = c[3];"),
+    ("philox: key schedule constant", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;"),
+    ("kp: cosine not squared", "double l2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);",
+     "double l2 = -(log(u[0]) + c * log(u[2])) / (2.0 * alpha);"),
+    ("heatbath: beta not scaled by 2/3",
+     "if (kp_draw(2.0 * beta * k / 3.0, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;",
+     "if (kp_draw(beta * k, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;"),
+    ("heatbath: staple misses its lower half",
+     "        su3_dag_mul(m, U + (xmnu * 4 + nu) * 9, t2);\n        for (int k = 0; k < 9; ++k) A[k] += t2[k];",
+     "        su3_dag_mul(m, U + (xmnu * 4 + nu) * 9, t2);"),
     ("plaquette misses a conjugate",
      "acc += ab[i * 3 + k] * conj(e[j * 3 + k]);",
      "acc += ab[i * 3 + k] * e[j * 3 + k];"),
@@ -95,16 +104,21 @@ FAST = {
     "pin_solvers_lapack": dict(dims=(2, 4, 2, 4), maxiter=400),
     "pin_free_field_solve": dict(dims=(4, 2, 4, 4)),
     "pin_gamma5_hermiticity": dict(dims=(2, 4, 2, 4)),
+    "pin_heatbath_unitary_and_strong_coupling": dict(dims=(2, 2, 2, 4)),
+    "pin_eo_solve_odd_rows": dict(dims=(2, 2, 4, 4)),
 }
 
 
-def _caught(orc):
+def _caught(orc, first=False):
+    """Pins that fail on `orc` (with `first`, stop at the first one)."""
     failures = []
     for pin in pins.ALL_PINS:
         try:
             pin(orc, **FAST.get(pin.__name__, {}))
         except Exception as e:  # noqa: BLE001 - any failure counts as caught
             failures.append((pin.__name__, type(e).__name__))
+            if first:
+                break
     return failures
 
 
@@ -121,7 +135,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
     lib = oracle.compile_copy(src.replace(old, new, 1),
                               str(tmp_path / "liboracle_mutant.so"))
     orc = oracle.Oracle(lib)
-    failures = _caught(orc)
+    failures = _caught(orc, first=True)
     assert failures, "no pin caught the planted mistake: %s" % name
 
 
