@@ -338,6 +338,28 @@ size_t wl_meson_workspace_bytes(const int32_t dims[4]);
 int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0,
                          double *corr, void *work, size_t work_bytes, void *stream);
 
+/* Pure gauge theory (paper Sec. 3: the SU(3) heatbath of the pure-gauge side,
+ * after Creutz), on the CANONICAL complex128 gauge field U[V][4][3][3] on the
+ * device (the layout wl_pack_gauge reads), with the Wilson plaquette action
+ *   S = beta sum_P (1 - Re Tr U_P / 3).
+ * wl_heatbath: nsweeps heat-bath sweeps in place. A sweep updates, for
+ * mu = 0..3, the links of direction mu on the even and then the odd sites;
+ * each link gets the Cabibbo-Marinari update over its SU(2) subgroups on
+ * rows/columns (0,1), (1,2), (0,2), each drawn by the Kennedy-Pendleton
+ * algorithm (at most 64 attempts; a subgroup without an accepted draw keeps
+ * its link). Random numbers: Philox4x32-10 with key (seed, 0x68656174) and
+ * counter (site, mu + 4 subgroup + 16 attempt, sweep number, draw), sweep
+ * numbers sweep0, sweep0 + 1, ...; the result does not depend on the launch
+ * or on other work. Asynchronous on `stream`.
+ * wl_plaquette: the mean plaquette sum_x sum_{mu<nu} Re Tr U_mu nu(x) / (18 V)
+ * into *out (device double), through wl_plaquette_workspace_bytes(dims) of
+ * work; fixed-order sums (bitwise reproducible). Asynchronous on `stream`. */
+int wl_heatbath(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
+                uint32_t sweep0, uint32_t seed, void *stream);
+size_t wl_plaquette_workspace_bytes(const int32_t dims[4]);
+int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *work,
+                 size_t work_bytes, void *stream);
+
 /* Streaming device-to-device copy of `bytes` bytes (both pointers 16-byte
  * aligned, bytes a multiple of 16; the buffers must not overlap), loads then
  * non-temporal stores, 64 bytes per thread: the achievable-bandwidth

@@ -18,7 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwilson.so")
 
 SOURCES = ["wl_api.hip", "wl_dslash.hip", "wl_hop_f64.hip", "wl_hop_f32.hip", "wl_hop_f16.hip",
-           "wl_blas.hip", "wl_solver.hip", "wl_server.hip", "wl_meson.hip"]
+           "wl_blas.hip", "wl_solver.hip", "wl_server.hip", "wl_meson.hip",
+           "wl_gauge.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CFLAGS = [

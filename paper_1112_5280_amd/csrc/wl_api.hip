@@ -590,6 +590,40 @@ int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0, d
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_meson_correlators");
 }
 
+int wl_heatbath(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
+                uint32_t sweep0, uint32_t seed, void *stream) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why)) return fail(WL_EINVAL, why);
+    if (!gauge) return fail(WL_EINVAL, "NULL buffer");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(WL_EINVAL, "beta must be positive");
+    if (nsweeps < 0) return fail(WL_EINVAL, "nsweeps must be >= 0");
+    const hipError_t e = launch_heatbath(g, gauge, beta, nsweeps, sweep0, seed,
+                                         static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_heatbath");
+}
+
+size_t wl_plaquette_workspace_bytes(const int32_t dims[4]) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why)) return 0;
+    return plaquette_workspace_bytes(g);
+}
+
+int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *work,
+                 size_t work_bytes, void *stream) {
+    Geom g;
+    std::string why;
+    if (!make_geom(dims, &g, &why)) return fail(WL_EINVAL, why);
+    if (!gauge || !out || !work) return fail(WL_EINVAL, "NULL buffer");
+    const size_t need = plaquette_workspace_bytes(g);
+    if (work_bytes < need)
+        return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                       " bytes, got " + std::to_string(work_bytes));
+    const hipError_t e = launch_plaquette(g, gauge, out, work, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_plaquette");
+}
+
 int wl_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {
     if (!src || !dst) return fail(WL_EINVAL, "NULL buffer");
     const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);

@@ -49,7 +49,8 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_server_create", "wl_server_submit", "wl_server_wait", "wl_server_next",
            "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy",
            "solve_cg_noalloc", "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
-           "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators")
+           "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators",
+           "wl_heatbath", "wl_plaquette_workspace_bytes", "wl_plaquette")
 
 
 class WilsonError(RuntimeError):
@@ -119,6 +120,12 @@ def _load():
     for f in (lib.solve_cg_tm, lib.solve_bicgstab_tm):
         f.argtypes = [P, P, P, P, D, D, P, D, I32, U32, P, SZ, ctypes.POINTER(SolveStats), P]
         f.restype = ctypes.c_int
+    lib.wl_heatbath.argtypes = [P, P, D, I32, U32, U32, P]
+    lib.wl_heatbath.restype = ctypes.c_int
+    lib.wl_plaquette_workspace_bytes.argtypes = [P]
+    lib.wl_plaquette_workspace_bytes.restype = SZ
+    lib.wl_plaquette.argtypes = [P, P, P, P, SZ, P]
+    lib.wl_plaquette.restype = ctypes.c_int
     lib.wl_meson_workspace_bytes.argtypes = [P]
     lib.wl_meson_workspace_bytes.restype = SZ
     lib.wl_meson_correlators.argtypes = [P, P, I32, P, P, SZ, P]
@@ -175,6 +182,10 @@ def _ptr(t):
     if t is None:
         return None
     if isinstance(t, torch.Tensor):
+        if t.device.type != "cuda":
+            # every buffer of the ABI is device memory: a host pointer would
+            # reach a kernel and fault the GPU
+            raise ValueError("a device tensor is required, got one on %s" % t.device)
         return ctypes.c_void_p(t.data_ptr())
     return ctypes.c_void_p(int(t))
 
@@ -382,7 +393,34 @@ def meson_correlators(props, dims, t0=0, work=None, stream=None):
                            dtype=torch.uint8, device=props.device)
     _check(lib.wl_meson_correlators(_ptr(props), _dims(dims), int(t0), _ptr(corr), _ptr(work),
                                     work.numel(), _stream(stream)), "wl_meson_correlators")
+    if stream is not None:
+        # both were allocated on the current stream; the kernel runs on `stream`
+        corr.record_stream(stream)
+        work.record_stream(stream)
     return torch.view_as_complex(corr)
+
+
+def heatbath(U, dims, beta, nsweeps=1, sweep0=0, seed=0, stream=None):
+    """nsweeps SU(3) heat-bath sweeps in place on the canonical complex128 field
+    U[V, 4, 3, 3] (a contiguous device tensor); asynchronous."""
+    V = int(np.prod(dims))
+    if (not isinstance(U, torch.Tensor) or U.dtype != torch.complex128 or not U.is_contiguous()
+            or tuple(U.shape) != (V, 4, 3, 3)):
+        raise ValueError("U must be a contiguous complex128 device tensor [V, 4, 3, 3]")
+    _check(lib.wl_heatbath(_ptr(U), _dims(dims), float(beta), int(nsweeps),
+                           int(sweep0) & 0xffffffff, int(seed) & 0xffffffff, _stream(stream)),
+           "wl_heatbath")
+
+
+def plaquette(U, dims, stream=None):
+    """Mean plaquette of the canonical complex128 device field U[V, 4, 3, 3]."""
+    out = torch.empty(1, dtype=torch.float64, device=U.device)
+    work = torch.empty(max(int(lib.wl_plaquette_workspace_bytes(_dims(dims))), 8),
+                       dtype=torch.uint8, device=U.device)
+    _check(lib.wl_plaquette(_ptr(U), _dims(dims), _ptr(out), _ptr(work), work.numel(),
+                            _stream(stream)), "wl_plaquette")
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    return float(out.cpu())
 
 
 def empty_batch(dims, nrhs, flags=F64, device="cuda"):

@@ -181,3 +181,14 @@ def test_noalloc_solve_rejects_before_touching_the_gpu(w):
     # the small configurations of the uneven batch fit
     for d in ((4, 4, 4, 4), (8, 8, 8, 8), (8, 8, 8, 16)):
         assert w.workspace_bytes(d, w.EO | w.MIXED) <= (64 << 20)
+
+
+def test_host_tensors_are_refused_before_any_call(w):
+    """The binding refuses host tensors where the ABI takes device buffers
+    (checked before the library is called: nothing launches)."""
+    import torch
+    U = torch.zeros((256, 4, 3, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        w.heatbath(U, (4, 4, 4, 4), 1.0)
+    with pytest.raises(ValueError):
+        w._ptr(torch.zeros(4))

@@ -1,0 +1,120 @@
+"""The pure-gauge kernels (paper Sec. 3: the SU(3) heat bath of the pure-gauge
+side) against the oracle: heat-bath sweeps from the same field, seed and sweep
+numbers give the oracle's links (same Philox counters, the same draws; FP64
+arithmetic in a different order, so agreement to rounding), and the mean
+plaquette kernel gives the oracle's plaquette."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1112_5280_amd import synth
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_1112_5280_amd import wilson
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return wilson
+
+
+def _oracle_spread(U0, dims, beta, nsweeps, sweep0, seed):
+    """How far the oracle's own chain moves when every element of its start is
+    perturbed by one part in 1e16 (about one ulp). The heat bath amplifies
+    rounding: a link's new value depends on the direction b/|b| of its staple
+    term, ill conditioned where |b| is small (strong coupling, rough fields),
+    and each update feeds the staples of the next. Measured on the CPU: after
+    3 sweeps about 6e-14 at beta 5.7, 6e-10 at beta 2, 9e-7 at beta 0.5."""
+    rng = np.random.default_rng(2024)
+    a = U0.copy()
+    oracle.heatbath(a, dims, beta, nsweeps, sweep0=sweep0, seed=seed)
+    b = U0 * (1 + 1e-16 * rng.standard_normal(U0.shape))
+    oracle.heatbath(b, dims, beta, nsweeps, sweep0=sweep0, seed=seed)
+    return a, float(np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("dims,beta", [((4, 4, 4, 4), 5.7), ((6, 4, 2, 8), 2.0),
+                                       ((4, 6, 4, 4), 0.5)],
+                         ids=["4^4-b5.7", "6x4x2x8-b2.0", "4x6x4x4-b0.5"])
+@pytest.mark.parametrize("nsweeps", [1, 3])
+def test_heatbath_matches_oracle(w, dims, beta, nsweeps):
+    """Same field, seed and sweep numbers: the kernels draw the oracle's random
+    numbers, so the links agree to FP64 rounding as the chain amplifies it --
+    within 100 times the oracle's own spread under a one-ulp perturbation of
+    the start (and 1e-12 absolute). Any mistake in an update moves links by
+    O(0.1); a flipped accept/reject decision would too."""
+    U0 = synth.gauge_haar(dims, 12)
+    Ud = torch.from_numpy(U0.copy()).to("cuda")
+    w.heatbath(Ud, dims, beta, nsweeps=nsweeps, sweep0=5, seed=77)
+    got = gu.to_np(Ud)
+    want, spread = _oracle_spread(U0, dims, beta, nsweeps, 5, 77)
+    tol = max(1e-12, 100 * spread)
+    assert np.abs(got - want).max() <= tol, (np.abs(got - want).max(), tol)
+    m = got.reshape(-1, 3, 3)
+    assert np.abs(np.linalg.det(m) - 1).max() < 1e-12
+    assert np.abs(m @ np.conj(np.swapaxes(m, 1, 2)) - np.eye(3)).max() < 1e-12
+    assert abs(w.plaquette(Ud, dims) - oracle.plaquette(got, dims)) <= 1e-14
+
+
+def test_heatbath_is_deterministic_and_composes(w):
+    """Two runs give the same bits, and 2 + 3 sweeps (sweep numbers 0-1 then
+    2-4) equal 5 sweeps in one call: a link's random numbers depend only on
+    (seed, sweep, site, direction), not on the launch."""
+    dims = (6, 4, 4, 6)
+    U0 = torch.from_numpy(synth.gauge_haar(dims, 5)).to("cuda")
+    a, b, c = U0.clone(), U0.clone(), U0.clone()
+    w.heatbath(a, dims, 3.0, nsweeps=5, sweep0=0, seed=4)
+    w.heatbath(b, dims, 3.0, nsweeps=5, sweep0=0, seed=4)
+    w.heatbath(c, dims, 3.0, nsweeps=2, sweep0=0, seed=4)
+    w.heatbath(c, dims, 3.0, nsweeps=3, sweep0=2, seed=4)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    d = U0.clone()
+    w.heatbath(d, dims, 3.0, nsweeps=5, sweep0=0, seed=5)
+    assert not torch.equal(a, d)
+
+
+def test_heatbath_argument_errors(w):
+    dims = (4, 4, 4, 4)
+    U = torch.from_numpy(synth.gauge_unit(dims)).to("cuda")
+    for bad in (dict(beta=0.0), dict(beta=-1.0), dict(beta=float("nan")),
+                dict(beta=1.0, nsweeps=-1)):
+        with pytest.raises(w.WilsonError):
+            w.heatbath(U, dims, **bad)
+    with pytest.raises(ValueError):
+        w.heatbath(U[:-1], dims, 1.0)
+    odd = torch.zeros((4 * 4 * 4 * 3, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(w.WilsonError):
+        w.heatbath(odd, (4, 4, 4, 3), 1.0)
+
+
+def test_plaquette_matches_oracle(w):
+    for dims, U in (((8, 8, 8, 8), synth.gauge_smooth((8, 8, 8, 8), 0.3, 0)),
+                    ((6, 4, 6, 10), synth.gauge_haar((6, 4, 6, 10), 3)),
+                    ((4, 4, 4, 4), synth.gauge_unit((4, 4, 4, 4)))):
+        Ud = torch.from_numpy(U).to("cuda")
+        p = w.plaquette(Ud, dims)
+        assert abs(p - oracle.plaquette(U, dims)) <= 1e-14, dims
+
+
+def test_thermalised_fields_and_solves(w):
+    """A field thermalised by the GPU heat bath at beta = 5.7 on 8^4 (cold
+    start, 60 sweeps) has a plaquette near the pure-gauge value (0.55 at this
+    beta), and the Wilson operator on it is well conditioned below the critical
+    kappa: CG converges to the oracle's residual."""
+    dims = (8, 8, 8, 8)
+    Ud = torch.from_numpy(synth.gauge_unit(dims)).to("cuda")
+    w.heatbath(Ud, dims, 5.7, nsweeps=60, sweep0=0, seed=1)
+    p = w.plaquette(Ud, dims)
+    assert 0.52 < p < 0.58, p
+    U = gu.to_np(Ud)
+    assert abs(p - oracle.plaquette(U, dims)) <= 1e-13
+    b = synth.gaussian_spinor(dims, 3)
+    G = w.pack_gauge(U, dims)
+    X = w.empty_spinor(dims)
+    st = w.solve_cg(G, w.pack_spinor(b, dims), X, dims, 0.155, flags=w.EO)
+    assert st["status"] == 0
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    assert oracle.true_residual(U, b, x, dims, 0.155) <= 1e-10
