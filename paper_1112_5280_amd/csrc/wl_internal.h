@@ -121,10 +121,22 @@ __device__ __forceinline__ T load_nt(const T *p) {
     return __builtin_nontemporal_load((GT *)p);
 }
 
+// Element i of chunk j (S elements each) of a T array: the chunk base is
+// uniform across the wave and stays in scalar registers; only the 32-bit
+// byte offset of element i lives per lane, instead of a 64-bit address pair.
+// S * sizeof(T) < 4 GiB (make_geom bounds the lattice).
+template <typename T>
+__device__ __forceinline__ const T *at32(const void *base, int j, int S, int i) {
+    const char *chunk = static_cast<const char *>(base) + size_t(j) * size_t(S) * sizeof(T);
+    return reinterpret_cast<const T *>(chunk + uint32_t(i) * uint32_t(sizeof(T)));
+}
+
 // NC complex numbers of site i: NC / CW arrays of S chunks of CW complex, then
 // (if NC % CW != 0) one array of S chunks holding the remaining NC % CW.
-// NT: read-once data (a streaming load that L2 need not keep).
-template <typename ST, int NC, int CW, bool NT = false>
+// NT: read-once data (a streaming load that L2 need not keep). O32: 32-bit
+// offsets (fewer address registers; it pays where registers are scarcest,
+// the FP64 hopping kernels).
+template <typename ST, int NC, int CW, bool NT = false, bool O32 = false>
 __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Real<ST>> *v) {
     using T = typename Vec<ST, CW>::T;
     using R = Real<ST>;
@@ -133,8 +145,9 @@ __device__ __forceinline__ void load_cplx(const void *base, int S, int i, cpx<Re
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         T c;
-        if constexpr (NT) c = load_nt(&p[j * S + i]);
-        else c = p[j * S + i];
+        const T *q = O32 ? at32<T>(base, j, S, i) : &p[j * S + i];
+        if constexpr (NT) c = load_nt(q);
+        else c = *q;
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
             v[CW * j + k].re = R(c[2 * k]);
@@ -198,9 +211,9 @@ __device__ __forceinline__ void store_cplx(void *base, int S, int i, const cpx<R
 // reciprocal 1/m it cannot overflow when m is an FP32 denormal -- which the
 // far sites of a point-source residual reach after a few iterations, since
 // every hop multiplies by kappa -- and so never turns 0 * inf into NaN.
-template <typename ST, bool NT = false>
+template <typename ST, bool NT = false, bool O32 = false>
 __device__ __forceinline__ void load_spinor(const void *blk, int S, int i, cpx<Real<ST>> v[12]) {
-    load_cplx<ST, 12, spinor_cw<ST>(), NT>(blk, S, i, v);
+    load_cplx<ST, 12, spinor_cw<ST>(), NT, O32>(blk, S, i, v);
     if constexpr (std::is_same<ST, Half>::value) {
         const float *sp = reinterpret_cast<const float *>(static_cast<const char *>(blk) +
                                                           size_t(S) * 48) + i;
@@ -236,10 +249,11 @@ __device__ __forceinline__ const void *link_block(const void *gauge, int S, int 
     return static_cast<const char *>(gauge) + size_t(par * 4 + mu) * NCL * cbytes<ST>() * S;
 }
 
-template <typename ST, int NCL, bool NT = false>
+template <typename ST, int NCL, bool NT = false, bool O32 = false>
 __device__ __forceinline__ void load_link_raw(const void *gauge, int S, int par, int mu, int i,
                                               cpx<Real<ST>> *u) {
-    load_cplx<ST, NCL, link_cw<ST, NCL>(), NT>(link_block<ST, NCL>(gauge, S, par, mu), S, i, u);
+    load_cplx<ST, NCL, link_cw<ST, NCL>(), NT, O32>(link_block<ST, NCL>(gauge, S, par, mu), S, i,
+                                                    u);
 }
 
 template <typename ST, int NCL>
