@@ -19,7 +19,8 @@ host threads); ``serving`` summarises the served streams. Everything else
 (every Dslash variant, the small configurations, the 12 point sources of a
 24^3 x 48 propagator and their meson correlators, the uneven batch of 64
 small lattices, the served Poisson streams by size, a twisted-mass solve, the
-autotuner's record) goes to stderr and to gpurun_out/bench_detail.json.
+heat bath, plaquette and an overlapped configuration chain, the autotuner's
+record) goes to stderr and to gpurun_out/bench_detail.json.
 """
 import argparse
 import json
@@ -74,7 +75,8 @@ def log(*a):
 
 
 # the sources that define the hopping kernels (their code, layout and reductions)
-HOP_SOURCES = ("wl_hop.h", "wl_hop_f32.hip", "wl_dslash.hip", "wl_internal.h", "wl_reduce.h")
+HOP_SOURCES = ("wl_hop.h", "wl_hop_f32.hip", "wl_hop_f64.hip", "wl_dslash.hip", "wl_internal.h",
+               "wl_reduce.h")
 
 
 def kernel_source_hash():
@@ -87,10 +89,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(link12):
-    """Bytes per launch of the roofline kernel from the committed PMC summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when
-    the summary is for another kernel or the kernel sources changed since."""
+def profiled_traffic(link12, fp64=False):
+    """Bytes per launch of the FP32 (or, with fp64, the FP64) even-odd hop from
+    the committed PMC summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    copy's readings), or None when the summary is for another kernel or the
+    kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "hop_f32_eo_32x64_pmc.json")
     if link12 or not os.path.exists(path):
         return None
@@ -98,6 +101,8 @@ def profiled_traffic(link12):
         pm = json.load(f)
     if pm.get("source_hash") != kernel_source_hash():
         return None
+    if fp64:
+        return pm.get("fp64_eo_hop", {}).get("traffic_bytes_per_launch")
     return pm["traffic_bytes_per_launch"]
 
 
@@ -214,6 +219,60 @@ def batch12(w, torch, synth, n_launch):
                                               solves["batched_mixed_f32_eo"]["seconds"])
     out["autotuned_rhs_per_thread"] = w.tuning_report().strip().splitlines()
     del G, B, X, X1
+    torch.cuda.empty_cache()
+    return out
+
+
+def pure_gauge(w, torch, synth, np, U_host, dims, n_launch):
+    """The heat bath and the plaquette on the bench lattice, and the chain of
+    configurations with overlapped measurement (paper Sec. 3 and Sec. 4):
+    heat-bath sweep time, link updates per second, plaquette kernel time, and
+    the seconds per configuration of a 16^3 x 32 chain (2 sweeps per
+    configuration; its 12 point-source propagator solves and meson
+    correlators) with and without the two-stream overlap, whose correlators
+    must agree bitwise."""
+    from paper_1112_5280_amd.ensemble import Ensemble
+    V = int(np.prod(dims))
+    U = torch.from_numpy(U_host).to("cuda")     # the bench field, heat-bathed in place
+    s = torch.cuda.current_stream()
+    sweep = [0]
+
+    def one_sweep():
+        w.heatbath(U, dims, 5.7, nsweeps=1, sweep0=sweep[0], seed=11, stream=s)
+        sweep[0] += 1
+    th = time_kernel(one_sweep, max(2, n_launch // 10), torch)
+    out = {"lattice": list(dims), "beta": 5.7,
+           "heatbath_ms_per_sweep": th * 1e3,
+           "link_updates_per_s": 4 * V / th,
+           "heatbath_note": "one sweep = 8 launches (4 directions x 2 parities), each link "
+                            "3 SU(2) subgroup draws (Kennedy-Pendleton) from its 6 staples"}
+    out_d = torch.empty(1, dtype=torch.float64, device="cuda")
+    pw = torch.empty(max(int(w.lib.wl_plaquette_workspace_bytes(w._dims(dims))), 8),
+                     dtype=torch.uint8, device="cuda")
+    tp = time_kernel(lambda: w.lib.wl_plaquette(w._ptr(U), w._dims(dims), w._ptr(out_d),
+                                                w._ptr(pw), pw.numel(), w._stream(s)),
+                     n_launch, torch)
+    out.update({"plaquette": w.plaquette(U, dims), "plaquette_us": tp * 1e6,
+                "plaquette_GBs": 4 * V * 144 / tp / 1e9})
+    del U, pw
+    torch.cuda.empty_cache()
+    d2 = (16, 16, 16, 32)
+    U0 = synth.gauge_unit(d2)
+    chain = {}
+    for ov in (True, False):
+        e = Ensemble(U0, d2, 5.7, sweeps=2, kappa=0.12, site=0, seed=3, overlap=ov)
+        e.run(1)                                    # warm-up: tuning, graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        corr = e.run(4)
+        chain[ov] = (corr, (time.perf_counter() - t) / 4, e.stats[-1])
+        del e
+    assert torch.equal(chain[True][0], chain[False][0])
+    out["chain_16x16x16x32"] = {
+        "seconds_per_configuration_overlapped": chain[True][1],
+        "seconds_per_configuration_sequential": chain[False][1],
+        "iterations": max(x["iterations"] for x in chain[True][2]),
+        "correlators_bitwise_equal": True}
     torch.cuda.empty_cache()
     return out
 
@@ -611,7 +670,7 @@ def main():
     # the twisted-mass operator of the paper's action, mu = 0.01, with the
     # step's solver (mixed-precision eo-CG); the twist bounds sigma_min(M)
     # from below by 2 kappa mu, so it converges in fewer iterations
-    tm = None
+    tm_solve = None
     if not args.no_fp64_compare:
         mu = 0.01
         wk = torch.empty(w.workspace_bytes(dims, flags), dtype=torch.uint8, device="cuda")
@@ -622,8 +681,8 @@ def main():
                                               maxiter=20000, flags=flags, work=wk, stream=s),
                         torch)
         assert stt["status"] == 0 and stt["true_res"] <= 1e-10, stt
-        tm = {"mu": mu, "seconds": dt, "iterations": stt["iterations"],
-              "true_res": stt["true_res"], "algorithmic_GBs": stt["bytes"] / dt / 1e9}
+        tm_solve = {"mu": mu, "seconds": dt, "iterations": stt["iterations"],
+                    "true_res": stt["true_res"], "algorithmic_GBs": stt["bytes"] / dt / 1e9}
         del wk, Xt
 
     # Dslash variants, each timed over a run of launches (HIP events)
@@ -683,12 +742,17 @@ def main():
     per64 = Vh * (2 * 192 + 8 * lb64)
     roofline64 = {"bound": "hbm", "achieved": variants[dom64]["GBs"], "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": variants[dom64]["GBs"] / HBM_PEAK_GBS,
+                  "traffic": (profiled_traffic(args.link12, fp64=True)
+                              if args.workload == "32^3x64" else None),
                   "kernel": "wl::hop_kernel<double, %d, false, false, 0, 1, true> "
                             "(even-odd hop, FP64)" % (6 if args.link12 else 9),
                   "bytes_per_launch": per64, "avg_us": variants[dom64]["us"],
                   "gflops": variants[dom64]["GFLOPs"]}
 
     small = None if args.no_small else small_configs(w, torch, synth, args.kernel_launches)
+
+    gauge = None if args.no_small else pure_gauge(w, torch, synth, np, U, dims,
+                                                   args.kernel_launches)
 
     batch = uneven = None
     if not args.no_batch:
@@ -771,7 +835,8 @@ def main():
         "fp64_solve": fp64,
         "mixed_f16_solve": f16,
         "link12_solves": link12_solves,
-        "twisted_mass_solve": tm,
+        "twisted_mass_solve": tm_solve,
+        "pure_gauge": gauge,
         "dslash_variants": variants,
         "device_copy": copy,
         "roofline": roofline,
@@ -832,7 +897,7 @@ def main():
         "roofline": pick(roofline, "bound", "achieved", "peak", "unit", "frac", "traffic",
                          "kernel", "bytes_per_launch", "avg_us"),
         "roofline_fp64_eo": pick(roofline64, "bound", "achieved", "peak", "unit", "frac",
-                                 "kernel", "bytes_per_launch", "avg_us"),
+                                 "traffic", "kernel", "bytes_per_launch", "avg_us"),
         "cpu_baseline": pick(cpu, "value", "unit", "cores", "kind", "sample",
                              "seconds_per_iteration", "seconds_per_apply",
                              "seconds_per_apply_1_core"),
