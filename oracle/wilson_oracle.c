@@ -522,18 +522,32 @@ static void uniforms4(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
     for (int i = 0; i < 4; ++i) u[i] = ((double)o[i] + 0.5) / 4294967296.0;
 }
 
-/* Kennedy-Pendleton: x0 in [-1, 1] with density ~ sqrt(1 - x0^2) exp(alpha x0).
-   Candidate lambda^2 = -(ln r1 + cos^2(2 pi r2) ln r3) / (2 alpha), accepted
-   when r4^2 <= 1 - lambda^2; x0 = 1 - 2 lambda^2. Attempt n draws its four
-   uniforms from the counter (site, tag + 16 n, sweep, 0). Returns 0 and sets
-   *x0 when accepted within HB_MAX_TRIES attempts, else -1. */
-#define HB_MAX_TRIES 64
+/* x0 in [-1, 1] with density ~ sqrt(1 - x0^2) exp(alpha x0), alpha >= 0, by
+   rejection. For alpha >= 1 the Kennedy-Pendleton candidate:
+   lambda^2 = -(ln r1 + cos^2(2 pi r2) ln r3) / (2 alpha), accepted when
+   r4^2 <= 1 - lambda^2, x0 = 1 - 2 lambda^2. For alpha < 1, where that
+   candidate is seldom accepted (3.6 % of attempts at alpha = 0.1), the first
+   coordinate of a uniform point of the unit disk, x0 = sqrt(r1) cos(2 pi r2)
+   (density ~ sqrt(1 - x0^2)), accepted when r3 <= exp(alpha (x0 - 1)).
+   Either way an attempt is accepted with probability >= 0.41, so all
+   HB_MAX_TRIES attempts fail with probability below 1e-29. Attempt n draws
+   its four uniforms from the counter (site, tag + 16 n, sweep, 0). Returns 0
+   and sets *x0 when accepted, else -1. */
+#define HB_MAX_TRIES 128
 static int kp_draw(double alpha, uint32_t site, uint32_t tag, uint32_t sweep,
                    const uint32_t key[2], double *x0)
 {
     for (uint32_t n = 0; n < HB_MAX_TRIES; ++n) {
         double u[4];
         uniforms4(site, tag + 16u * n, sweep, 0u, key, u);
+        if (alpha < 1.0) {
+            double x = sqrt(u[0]) * cos(2.0 * M_PI * u[1]);
+            if (u[2] <= exp(alpha * (x - 1.0))) {
+                *x0 = x;
+                return 0;
+            }
+            continue;
+        }
         double c = cos(2.0 * M_PI * u[1]);
         double l2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
         if (u[3] * u[3] <= 1.0 - l2) {
@@ -544,7 +558,8 @@ static int kp_draw(double alpha, uint32_t site, uint32_t tag, uint32_t sweep,
     return -1;
 }
 
-/* Samples of the Kennedy-Pendleton draw for one alpha (to pin its density). */
+/* Samples of the x0 draw for one alpha (to pin its density); 2 marks a draw
+   that found no accepted candidate. */
 void orc_kp_samples(double alpha, int n, uint32_t seed, double *out)
 {
     uint32_t key[2] = {seed, 0x6b707070u};
@@ -630,7 +645,9 @@ static void staple_sum(const cplx *U, const int L[4], long s, int mu, cplx A[9])
    Kennedy-Pendleton draw, (X1, X2, X3) uniform on the sphere of radius
    sqrt(1 - X0^2) (cos theta = 2 u - 1, phi = 2 pi v from the counter
    (site, tag, sweep, 1)). Then U <- R U, R = r on rows (i, j). A subgroup
-   whose draw is not accepted within HB_MAX_TRIES attempts is left as it is. */
+   whose draw is not accepted within HB_MAX_TRIES attempts is left as it is.
+   A staple term with k = 0 leaves V undefined and the density of r flat:
+   r = X with alpha = 0 (Haar-uniform). */
 static void hb_link(cplx *U, const int L[4], long s, int mu, double beta,
                     uint32_t sweep, const uint32_t key[2])
 {
@@ -646,7 +663,10 @@ static void hb_link(cplx *U, const int L[4], long s, int mu, double beta,
         double b0 = creal(w00 + w11) / 2, b1 = -cimag(w01 + w10) / 2;
         double b2 = creal(w10 - w01) / 2, b3 = -cimag(w00 - w11) / 2;
         double k = sqrt(b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3);
-        if (!(k > 0.0)) continue;
+        if (!(k > 0.0)) {   /* V = 1 */
+            k = 0.0;
+            b0 = 1.0; b1 = b2 = b3 = 0.0;
+        }
         uint32_t tag = (uint32_t)mu | ((uint32_t)g << 2);
         double x0;
         if (kp_draw(2.0 * beta * k / 3.0, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;
@@ -655,7 +675,8 @@ static void hb_link(cplx *U, const int L[4], long s, int mu, double beta,
         double ct = 2.0 * d[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
         double ph = 2.0 * M_PI * d[1], rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
         double x1 = rad * st * cos(ph), x2 = rad * st * sin(ph), x3 = rad * ct;
-        double v0 = b0 / k, v1 = b1 / k, v2 = b2 / k, v3 = b3 / k;
+        double n = k > 0.0 ? k : 1.0;
+        double v0 = b0 / n, v1 = b1 / n, v2 = b2 / n, v3 = b3 / n;
         cplx X[4] = {x0 + I * x3, x2 + I * x1, -x2 + I * x1, x0 - I * x3};
         cplx Vm[4] = {v0 + I * v3, v2 + I * v1, -v2 + I * v1, v0 - I * v3};
         cplx r[4] = {X[0] * Vm[0] + X[1] * Vm[2], X[0] * Vm[1] + X[1] * Vm[3],

@@ -16,7 +16,9 @@ def pytest_configure(config):
 
 
 if os.environ.get("PYTEST_XDIST_WORKER"):
-    # parallel workers share the CPUs: one BLAS thread each, else the dense
-    # LAPACK pins oversubscribe the cores and run many times slower
+    # parallel workers share the CPUs: one BLAS and one OpenMP thread each
+    # (the oracle's OpenMP runtime reads the variable when it loads, after
+    # this file), else the workers oversubscribe the cores and spin
+    os.environ["OMP_NUM_THREADS"] = "1"
     from threadpoolctl import threadpool_limits
     _BLAS_LIMIT = threadpool_limits(1)

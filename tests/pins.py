@@ -479,15 +479,22 @@ def pin_philox_known_answers(orc):
 
 
 def pin_kp_density(orc):
-    """The Kennedy-Pendleton draw samples x0 with density proportional to
-    sqrt(1 - x0^2) exp(alpha x0) on [-1, 1]: its mean is I_2(alpha)/I_1(alpha),
-    and a Kolmogorov-Smirnov test against the numerically integrated
-    distribution function accepts it."""
+    """The heat bath's x0 draw samples the density proportional to
+    sqrt(1 - x0^2) exp(alpha x0) on [-1, 1] (Kennedy-Pendleton for alpha >= 1,
+    rejection from the unit disk's first coordinate below): every draw is
+    accepted, the mean is I_2(alpha)/I_1(alpha), and a Kolmogorov-Smirnov test
+    against the numerically integrated distribution function accepts it --
+    at alpha = 0 (the semicircle), in the strong-coupling range where
+    Kennedy-Pendleton alone is seldom accepted, and on both sides of the
+    switch at alpha = 1."""
     from scipy import integrate, special, stats
     n = 200000
-    for alpha in (0.4, 2.5, 12.0):
+    x = orc.kp_samples(0.0, n, seed=5)
+    assert (np.abs(x) <= 1).all()
+    assert abs(x.mean()) < 5 * 0.5 / np.sqrt(n)
+    for alpha in (0.05, 0.4, 0.99, 1.0, 2.5, 12.0):
         x = orc.kp_samples(alpha, n, seed=5)
-        assert (np.abs(x) <= 1).all()
+        assert (np.abs(x) <= 1).all(), alpha
         mean = special.iv(2, alpha) / special.iv(1, alpha)
         z = integrate.quad(lambda t: np.sqrt(1 - t * t) * np.exp(alpha * t), -1, 1)[0]
         m2 = integrate.quad(lambda t: t * t * np.sqrt(1 - t * t) * np.exp(alpha * t), -1, 1)[0] / z

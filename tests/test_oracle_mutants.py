@@ -86,6 +86,13 @@ MUTANTS = [
     ("philox: key schedule constant", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE86u;"),
     ("kp: cosine not squared", "double l2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);",
      "double l2 = -(log(u[0]) + c * log(u[2])) / (2.0 * alpha);"),
+    ("x0 draw: disk radius not a square root",
+     "double x = sqrt(u[0]) * cos(2.0 * M_PI * u[1]);",
+     "double x = u[0] * cos(2.0 * M_PI * u[1]);"),
+    ("x0 draw: disk acceptance sign", "if (u[2] <= exp(alpha * (x - 1.0))) {",
+     "if (u[2] <= exp(-alpha * (x - 1.0))) {"),
+    ("x0 draw: switch to Kennedy-Pendleton too early", "if (alpha < 1.0) {",
+     "if (alpha < 0.01) {"),
     ("heatbath: beta not scaled by 2/3",
      "if (kp_draw(2.0 * beta * k / 3.0, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;",
      "if (kp_draw(beta * k, (uint32_t)s, tag, sweep, key, &x0) != 0) continue;"),
