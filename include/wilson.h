@@ -345,9 +345,11 @@ int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0,
  * wl_heatbath: nsweeps heat-bath sweeps in place. A sweep updates, for
  * mu = 0..3, the links of direction mu on the even and then the odd sites;
  * each link gets the Cabibbo-Marinari update over its SU(2) subgroups on
- * rows/columns (0,1), (1,2), (0,2), each drawn by the Kennedy-Pendleton
- * algorithm (at most 64 attempts; a subgroup without an accepted draw keeps
- * its link). Random numbers: Philox4x32-10 with key (seed, 0x68656174) and
+ * rows/columns (0,1), (1,2), (0,2), whose SU(2) heat-bath component x0 is
+ * drawn by rejection (Kennedy-Pendleton for alpha = 2 beta |b| / 3 >= 1, the
+ * unit disk's first coordinate below; at most 128 attempts, each accepted
+ * with probability >= 0.41; a subgroup without an accepted draw keeps its
+ * link). Random numbers: Philox4x32-10 with key (seed, 0x68656174) and
  * counter (site, mu + 4 subgroup + 16 attempt, sweep number, draw), sweep
  * numbers sweep0, sweep0 + 1, ...; the result does not depend on the launch
  * or on other work. Asynchronous on `stream`.

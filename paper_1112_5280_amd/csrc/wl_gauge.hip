@@ -11,8 +11,12 @@
 // sum) and w its 2 x 2 block, the SU(2) element is r = X V, V the SU(2)
 // direction of b = (Re(w00 + w11), -Im(w01 + w10), Re(w10 - w01),
 // -Im(w00 - w11)) / 2, and X drawn with density exp(alpha X0), alpha =
-// 2 beta |b| / 3: X0 by Kennedy-Pendleton, the other three components uniform
-// on their sphere. Random numbers come from Philox4x32-10 keyed by the seed,
+// 2 beta |b| / 3: X0 from its density sqrt(1 - X0^2) exp(alpha X0) by
+// rejection (Kennedy-Pendleton candidates for alpha >= 1; below, where those
+// are seldom accepted, the first coordinate of a uniform point of the unit
+// disk, accepted with probability exp(alpha (X0 - 1))), the other three
+// components uniform on their sphere; a zero b (V undefined) gives alpha = 0
+// and V = 1. Random numbers come from Philox4x32-10 keyed by the seed,
 // with counters (site, mu + 4 subgroup + 16 attempt, sweep, draw), so a link's
 // update does not depend on the launch shape or on the other links' timing.
 #include "wl_reduce.h"
@@ -50,7 +54,9 @@ __device__ __forceinline__ void unif4(uint32_t a, uint32_t b, uint32_t c, uint32
     for (int i = 0; i < 4; ++i) u[i] = (double(o[i]) + 0.5) * (1.0 / 4294967296.0);
 }
 
-constexpr int kHbTries = 64;
+// rejection attempts per draw: each is accepted with probability >= 0.41, so
+// a draw fails (and its subgroup keeps the link) with probability < 1e-29
+constexpr int kHbTries = 128;
 
 struct GaugeArgs {
     double2 *U;          // [V][4][9] complex
@@ -154,18 +160,26 @@ __global__ void __launch_bounds__(kBlock) heatbath_kernel(GaugeArgs a) {
         const double b0 = 0.5 * (w00.re + w11.re), b1 = -0.5 * (w01.im + w10.im);
         const double b2 = 0.5 * (w10.re - w01.re), b3 = -0.5 * (w00.im - w11.im);
         const double k = sqrt(b0 * b0 + b1 * b1 + b2 * b2 + b3 * b3);
-        if (!(k > 0.0)) continue;
+        const bool flat = !(k > 0.0);              // V = 1, alpha = 0
         const uint32_t tag = uint32_t(mu) | (uint32_t(gidx) << 2);
-        const double alpha = 2.0 * a.beta * k / 3.0;
+        const double alpha = flat ? 0.0 : 2.0 * a.beta * k / 3.0;
         double x0 = 2.0;
-        for (int n = 0; n < kHbTries; ++n) {   // Kennedy-Pendleton, bounded attempts
+        for (int n = 0; n < kHbTries; ++n) {
             double q[4];
             unif4(uint32_t(s), tag + 16u * uint32_t(n), a.sweep, 0u, a.k0, a.k1, q);
-            const double cs = cos(2.0 * M_PI * q[1]);
-            const double l2 = -(log(q[0]) + cs * cs * log(q[2])) / (2.0 * alpha);
-            if (q[3] * q[3] <= 1.0 - l2) {
-                x0 = 1.0 - 2.0 * l2;
-                break;
+            if (alpha < 1.0) {                     // unit disk, exp(alpha (x - 1))
+                const double x = sqrt(q[0]) * cos(2.0 * M_PI * q[1]);
+                if (q[2] <= exp(alpha * (x - 1.0))) {
+                    x0 = x;
+                    break;
+                }
+            } else {                               // Kennedy-Pendleton
+                const double cs = cos(2.0 * M_PI * q[1]);
+                const double l2 = -(log(q[0]) + cs * cs * log(q[2])) / (2.0 * alpha);
+                if (q[3] * q[3] <= 1.0 - l2) {
+                    x0 = 1.0 - 2.0 * l2;
+                    break;
+                }
             }
         }
         if (x0 > 1.0) continue;   // no acceptance: this subgroup keeps its link
@@ -174,7 +188,8 @@ __global__ void __launch_bounds__(kBlock) heatbath_kernel(GaugeArgs a) {
         const double ct = 2.0 * d[0] - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
         const double ph = 2.0 * M_PI * d[1], rad = sqrt(fmax(0.0, 1.0 - x0 * x0));
         const double x1 = rad * st * cos(ph), x2 = rad * st * sin(ph), x3 = rad * ct;
-        const double v0 = b0 / k, v1 = b1 / k, v2 = b2 / k, v3 = b3 / k;
+        const double v0 = flat ? 1.0 : b0 / k, v1 = flat ? 0.0 : b1 / k;
+        const double v2 = flat ? 0.0 : b2 / k, v3 = flat ? 0.0 : b3 / k;
         const C X[4] = {{x0, x3}, {x2, x1}, {-x2, x1}, {x0, -x3}};
         const C Vm[4] = {{v0, v3}, {v2, v1}, {-v2, v1}, {v0, -v3}};
         const C rr[4] = {X[0] * Vm[0] + X[1] * Vm[2], X[0] * Vm[1] + X[1] * Vm[3],

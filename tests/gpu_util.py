@@ -1,5 +1,7 @@
 """Helpers shared by the GPU parity tests (test infrastructure)."""
 import numpy as np
+
+import oracle
 import torch
 
 # Bars from the problem statement: FP64 operators agree with the FP64 oracle to
@@ -48,3 +50,18 @@ def parity_of_sites(dims):
     t, z, y, x = np.meshgrid(np.arange(lt), np.arange(lz), np.arange(ly), np.arange(lx),
                              indexing="ij")
     return ((x + y + z + t) % 2).reshape(-1)
+
+
+def heatbath_spread(U0, dims, beta, nsweeps, sweep0, seed):
+    """How far the oracle's own chain moves when every element of its start is
+    perturbed by one part in 1e16 (about one ulp). The heat bath amplifies
+    rounding: a link's new value depends on the direction b/|b| of its staple
+    term, ill conditioned where |b| is small (strong coupling, rough fields),
+    and each update feeds the staples of the next. Measured on the CPU: after
+    3 sweeps about 6e-14 at beta 5.7, 6e-10 at beta 2, 9e-7 at beta 0.5."""
+    rng = np.random.default_rng(2024)
+    a = U0.copy()
+    oracle.heatbath(a, dims, beta, nsweeps, sweep0=sweep0, seed=seed)
+    b = U0 * (1 + 1e-16 * rng.standard_normal(U0.shape))
+    oracle.heatbath(b, dims, beta, nsweeps, sweep0=sweep0, seed=seed)
+    return a, float(np.abs(a - b).max())

@@ -180,3 +180,18 @@ def test_point_sources_fp16_inner_24x48(w):
     assert st["status"] == 0, st
     assert st["iterations"] == stats[5]["iterations"]
     assert torch.equal(one, w.batch_field(X, dims, 0, 5))
+
+
+def test_heatbath_one_sweep_32x64(w, cfg3):
+    """The bench lattice (32^3 x 64, its exp(i 0.35 H) field, beta = 5.7): one
+    sweep in the launch configuration the bench times, every link against the
+    oracle's sweep within 100 times the oracle's own one-ulp spread, and the
+    plaquette of the result."""
+    dims, U0 = cfg3["dims"], cfg3["U"]
+    Ud = torch.from_numpy(U0).to("cuda")
+    w.heatbath(Ud, dims, 5.7, nsweeps=1, sweep0=3, seed=21)
+    got = gu.to_np(Ud)
+    want, spread = gu.heatbath_spread(U0, dims, 5.7, 1, 3, 21)
+    err = np.abs(got - want).max()
+    assert err <= max(1e-12, 100 * spread), (err, spread)
+    assert abs(w.plaquette(Ud, dims) - oracle.plaquette(got, dims)) <= 1e-13
