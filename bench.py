@@ -380,9 +380,10 @@ def small_configs(w, torch, synth, n_launch):
                     (w.EO | w.MIXED | w.F16S, "bicgstab_eo_mixed_f16"), (w.EO, "cg_eo_f64"),
                     (w.EO | w.MIXED, "cg_eo_mixed_f32")):
         fn = w.solve_bicgstab if name.startswith("bicgstab") else w.solve_cg
-        st, dt = timed(lambda: fn(G, B, X, dims, kappa, maxiter=20000, flags=f, stream=s), torch)
+        st, dt = timed(lambda: fn(G, B, X, dims, kappa, maxiter=60000, flags=f, stream=s), torch)
         solves[name] = {"ms": dt * 1e3, "status": st["status_name"], "iterations": st["iterations"],
-                        "restarts": st["restarts"], "true_res": st["true_res"]}
+                        "fp64_iterations": st["fp64_iterations"], "restarts": st["restarts"],
+                        "true_res": st["true_res"]}
     out["16^3x32"] = {"lattice": list(dims), "kappa": kappa, "cache_resident": True,
                       "operators": ops, "solves": solves}
     return out
