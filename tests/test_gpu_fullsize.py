@@ -195,3 +195,47 @@ def test_heatbath_one_sweep_32x64(w, cfg3):
     err = np.abs(got - want).max()
     assert err <= max(1e-12, 100 * spread), (err, spread)
     assert abs(w.plaquette(Ud, dims) - oracle.plaquette(got, dims)) <= 1e-13
+
+
+def test_twisted_mass_32x64(w, cfg3):
+    """The bench's twisted-mass configuration (mu = 0.01 on the 32^3 x 64
+    field): M(mu) and M(mu)^dag in FP64 and FP32 on every site against the
+    oracle's operator, and the mixed-precision even-odd solve the bench times
+    to the oracle's true residual 1e-10."""
+    dims, kappa, U, b = cfg3["dims"], cfg3["kappa"], cfg3["U"], cfg3["b"]
+    mu = 0.01
+    for prec in (0x0, 0x1):
+        G = w.pack_gauge(U, dims, prec)
+        P = w.pack_spinor(b, dims, prec)
+        O = w.empty_spinor(dims, prec)
+        for dag in (False, True):
+            w.wilson_dslash_tm(G, P, O, dims, kappa, mu, flags=prec | (w.DAG if dag else 0))
+            got = gu.to_np(w.unpack_spinor(O, dims, prec))
+            want = oracle.mop_tm(U, b, dims, kappa, mu, dagger=dag)
+            gu.assert_close(got, want, gu.TOL[prec], "M(mu) prec=%d dag=%d" % (prec, dag))
+        del G, P, O
+    G = w.pack_gauge(U, dims)
+    X = w.empty_spinor(dims)
+    st = w.solve_cg_tm(G, w.pack_spinor(b, dims), X, dims, kappa, mu, tol=1e-10, maxiter=20000,
+                       flags=w.EO | w.MIXED)
+    assert st["status"] == 0, st
+    x = gu.to_np(w.unpack_spinor(X, dims))
+    assert oracle.true_residual_tm(U, b, x, dims, kappa, mu) <= 1e-10
+
+
+def test_meson_correlators_24x48(w):
+    """Eq. 1's contraction at the size the bench times (12 propagator columns
+    of the 24^3 x 48 lattice, source slice t0 = 7) on seeded Gaussian columns,
+    against the oracle's contraction: FP64 sums in different orders agree to
+    1e-12 of the largest correlator."""
+    dims, t0 = (24, 24, 24, 48), 7
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(31)
+    props = rng.standard_normal((12, V, 4, 3)) + 1j * rng.standard_normal((12, V, 4, 3))
+    B = w.empty_batch(dims, 12)
+    for r in range(12):
+        w.pack_spinor(props[r], dims, out=w.batch_field(B, dims, 0, r))
+    got = w.meson_correlators(B, dims, t0).cpu().numpy()
+    oracle.set_threads(max(1, len(os.sched_getaffinity(0))))
+    want = oracle.meson(props, dims, t0)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
