@@ -91,6 +91,36 @@ def test_even_odd(w, dims, prec, link):
             gu.assert_close(mid[~sel], want[~sel], gu.TOL[prec], "schur intermediate p=%d" % p)
 
 
+@pytest.mark.parametrize("dims", [(128, 2, 2, 4), (132, 2, 2, 4), (2, 34, 2, 4), (10, 6, 4, 6)],
+                         ids=["Lx128-widest-window", "Lx132-no-window", "Lx2-Ly34", "10x6x4x6"])
+@pytest.mark.parametrize("prec", [0x0, 0x1], ids=["f64", "f32"])
+def test_lds_window_edges(w, dims, prec):
+    """The x/y neighbour window of the FP64 and FP32 kernels at its edges: the
+    widest row it stages (Lx/2 = 64), a row too wide for it (global loads
+    throughout), rows of one site with many y wraps, and blocks that straddle
+    rows and end in the padding of the last block; full operator and both
+    even-odd hops against the oracle."""
+    kappa = 0.133
+    phases = PHASES[1]
+    U, psi = _fields(dims, 5)
+    G = w.pack_gauge(U, dims, prec)
+    P = w.pack_spinor(psi, dims, prec)
+    out = w.empty_spinor(dims, prec)
+    for dag in (False, True):
+        w.wilson_dslash(G, P, out, dims, kappa, phases, prec | (w.DAG if dag else 0))
+        got = gu.to_np(w.unpack_spinor(out, dims, prec))
+        gu.assert_close(got, oracle.mop(U, psi, dims, kappa, phases, dagger=dag), gu.TOL[prec],
+                        "M dag=%d %s" % (dag, dims))
+    par = gu.parity_of_sites(dims)
+    half = w.empty_spinor(dims, prec, 1)
+    for p in (0, 1):
+        w.wilson_dslash_eo(G, w.parity_block(P, dims, prec, 1 - p), half, dims, kappa, p,
+                           phases, prec | w.HOP)
+        got = gu.half_to_canon(w, half, dims, prec, p)
+        want = oracle.dslash_eo(U, psi, dims, p, phases)
+        gu.assert_close(got[par == p], want[par == p], gu.TOL[prec], "hop p=%d %s" % (p, dims))
+
+
 def test_pack_roundtrip(w):
     dims = (6, 4, 6, 10)
     psi = synth.gaussian_spinor(dims, 7)
