@@ -116,6 +116,15 @@ hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
             : call.red->epilogue == kEpiBiOmega ? kRedTS : kRedNorm;
         if (red == kRedDotAux && !call.aux[call.first_par]) return hipErrorInvalidValue;
         if (red == kRedTS && !call.xs[call.first_par]) return hipErrorInvalidValue;
+        if (call.cg[0]) {
+            if (call.red->epilogue != kEpiCgRr || !call.red->sc || !call.cg[1] || !call.cg[2] ||
+                call.npar != 1 || call.nrhs != 1 || !call.dag || !call.xs[call.first_par] ||
+                prec == WL_F16S)
+                return hipErrorInvalidValue;
+            red = kRedCgXR;
+        }
+    } else if (call.cg[0]) {
+        return hipErrorInvalidValue;
     }
     if (call.npar < 1 || call.npar > 2 || !call.out[call.first_par] ||
         !call.in[1 - call.first_par])

@@ -76,7 +76,9 @@ struct MinWaves {
     static constexpr int value = std::is_same<ST, double>::value ? WL_F64_WAVES : WL_F32_WAVES;
 };
 
-enum RedMode : int { kRedNone = 0, kRedNorm = 1, kRedDotAux = 2, kRedTS = 3 };
+// kRedCgXR: the CG update fused into the epilogue of the adjoint's last hop
+// (its output q is not stored): x += alpha p, r -= alpha q and ||r||^2
+enum RedMode : int { kRedNone = 0, kRedNorm = 1, kRedDotAux = 2, kRedTS = 3, kRedCgXR = 4 };
 
 template <typename R>
 struct HopArgs {
@@ -108,6 +110,7 @@ struct HopArgs {
     bool twist;
     R tx, ta, sx;
     bool lds;              // x/y neighbourhood staged in LDS (when the kernel has a window)
+    void *cgv[3];          // kRedCgXR: x, p, r blocks of the output parity
 };
 
 // LDS staging of neighbour halos. A block's output sites are kBlock
@@ -465,7 +468,8 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
         }
     }
 
-    constexpr int NS = RED == kRedNone ? 1 : (RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3));
+    constexpr int NS = (RED == kRedNone || RED == kRedNorm || RED == kRedCgXR) ? 1
+                     : (RED == kRedDotAux ? 2 : 3);
     double sums[NR][NS];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -568,7 +572,9 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
 #pragma unroll
                 for (int k = 0; k < 12; ++k) o[k] = c[r] * acc[r][k];
             }
-            store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo[r], g.S, i, o);
+            if constexpr (RED != kRedCgXR)
+                store_spinor<ST, WL_NT_STORE != 0>(static_cast<char *>(a.out[p]) + fo[r], g.S, i,
+                                                   o);
 
             double *sm = sums[r];
             if constexpr (RED == kRedNorm) {
@@ -583,6 +589,25 @@ __global__ void __launch_bounds__(kBlock, MinWaves<ST>::value) hop_kernel(HopArg
                     sm[0] += double(w[k].re) * double(o[k].re) + double(w[k].im) * double(o[k].im);
                     sm[1] += double(w[k].re) * double(o[k].im) - double(w[k].im) * double(o[k].re);
                 }
+            } else if constexpr (RED == kRedCgXR) {     // x += al p; r -= al q; ||r||^2
+                // the arithmetic of the separate update pass, on q in registers
+                static_assert(NR == 1, "the fused CG update takes one RHS per thread");
+                const R al = R(rhs_reduce(a.red, rhs0, a.nb_rhs).sc->alpha);
+                cpx<R> xu[12], pu[12], ru[12];
+                load_spinor<ST>(static_cast<const char *>(a.cgv[0]) + fo[r], g.S, i, xu);
+                load_spinor<ST>(static_cast<const char *>(a.cgv[1]) + fo[r], g.S, i, pu);
+                load_spinor<ST>(static_cast<const char *>(a.cgv[2]) + fo[r], g.S, i, ru);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    xu[k] = xu[k] + al * pu[k];
+                    ru[k] = ru[k] - al * o[k];
+                }
+                store_spinor<ST>(static_cast<char *>(a.cgv[0]) + fo[r], g.S, i, xu);
+                store_spinor<ST>(static_cast<char *>(a.cgv[2]) + fo[r], g.S, i, ru);
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    sm[0] += double(ru[k].re) * double(ru[k].re) +
+                             double(ru[k].im) * double(ru[k].im);
             } else if constexpr (RED == kRedTS) {       // <out, xs>, ||out||^2
                 static_assert(XPAY, "kRedTS needs the xpay source");
 #pragma unroll
@@ -724,7 +749,9 @@ static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12
     for (int q = 0; q < a.npar && safe; ++q) {
         const int po = a.first_par ^ q;
         const void *o = a.out[po];
-        if (o == a.in[0] || o == a.in[1] || o == a.xs[po] || o == a.aux[po]) safe = false;
+        if (o == a.in[0] || o == a.in[1] || o == a.xs[po] || o == a.aux[po] || o == a.cgv[0] ||
+            o == a.cgv[1] || o == a.cgv[2])
+            safe = false;
     }
     if (!safe) return launch_nr<ST, NCL, DAG, XPAY, RED>(a, def, s);
 
@@ -734,13 +761,16 @@ static hipError_t launch_tuned(const HopArgs<Real<ST>> &a, int prec, bool link12
     TuneEntry ent;
     ent.best = def;
     float best_t = 1e30f;
+    // the fused CG update changes x and r, so its candidates are timed on the
+    // plain operator (the same hops, q written to `out`); the update runs once
+    constexpr int TR = RED == kRedCgXR ? int(kRedNone) : RED;
     auto trial = [&](Shape sh) {
         if (err != hipSuccess) return;
         constexpr int kReps = 3;
-        err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);   // warm-up
+        err = launch_nr<ST, NCL, DAG, XPAY, TR>(a, sh, s);   // warm-up
         if (err == hipSuccess) err = hipEventRecord(e0, s);
         for (int k = 0; k < kReps && err == hipSuccess; ++k)
-            err = launch_nr<ST, NCL, DAG, XPAY, RED>(a, sh, s);
+            err = launch_nr<ST, NCL, DAG, XPAY, TR>(a, sh, s);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -789,7 +819,7 @@ static hipError_t launch_t(const HopArgs<Real<ST>> &a, const HopCall &call, int 
                            hipStream_t s) {
     const hipError_t e = launch_tuned<ST, NCL, DAG, XPAY, RED>(a, prec, link12, s);
     if (e != hipSuccess || RED == kRedNone) return e;
-    constexpr int NS = RED == kRedNorm ? 1 : (RED == kRedDotAux ? 2 : 3);
+    constexpr int NS = (RED == kRedNorm || RED == kRedCgXR) ? 1 : (RED == kRedDotAux ? 2 : 3);
     return launch_finish(a.red, NS, a.nb_rhs, a.nrhs, a.skip, s);
 }
 
@@ -800,6 +830,10 @@ static hipError_t launch_red(const HopArgs<Real<ST>> &a, const HopCall &call, in
     case kRedNone: return launch_t<ST, NCL, DAG, XPAY, kRedNone>(a, call, prec, link12, s);
     case kRedNorm: return launch_t<ST, NCL, DAG, XPAY, kRedNorm>(a, call, prec, link12, s);
     case kRedDotAux: return launch_t<ST, NCL, DAG, XPAY, kRedDotAux>(a, call, prec, link12, s);
+    case kRedCgXR:   // the last hop of an adjoint Schur apply (FP64 or FP32 storage)
+        if constexpr (DAG && XPAY && !std::is_same<ST, Half>::value)
+            return launch_t<ST, NCL, DAG, XPAY, kRedCgXR>(a, call, prec, link12, s);
+        return hipErrorInvalidValue;
     default:
         if constexpr (XPAY) return launch_t<ST, NCL, DAG, XPAY, kRedTS>(a, call, prec, link12, s);
         return hipErrorInvalidValue;
@@ -860,6 +894,7 @@ static hipError_t launch_storage(const Geom &g, int prec, bool link12, const Pha
     a.ta = R(call.ta);
     a.sx = R(call.sx);
     a.lds = g.Lxh <= kLdsHalo;
+    for (int q = 0; q < 3; ++q) a.cgv[q] = call.cg[q];
     const bool xpay = call.xs[call.first_par] != nullptr;
     return link12 ? launch_ncl<ST, 6>(a, call, prec, link12, call.dag, xpay, red, s)
                   : launch_ncl<ST, 9>(a, call, prec, link12, call.dag, xpay, red, s);

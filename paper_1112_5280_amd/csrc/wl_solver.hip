@@ -232,6 +232,43 @@ struct Space {
         applies += 1;
     }
 
+    // The CG step after t = A p: q = A^dag t, x += alpha p, r -= alpha q and
+    // ||r||^2 (kEpiCgRr). For one RHS on the even-odd system in FP64 or FP32
+    // storage the update runs in the epilogue of the adjoint's last hop and q
+    // is never stored (192 B per FP32 site and iteration less); otherwise, and
+    // bitwise alike, as the hop followed by the update pass.
+    void cg_step(const void *t, void *q, void *x, void *p, void *r, const int *skip) {
+        if (!(eo && nrhs == 1 && !gtab && prec != WL_F16S)) {
+            apply(t, q, true, kEpiNone, nullptr, skip);
+            blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+            return;
+        }
+        HopCall c1{};
+        c1.gauge = gauge;
+        c1.in[0] = t;
+        c1.out[1] = tmp;
+        c1.first_par = 1; c1.npar = 1; c1.dag = true; c1.skip = skip;
+        coef(c1, 1.0, 0);
+        if (tw != 0.0) {   // tmp = A^-dag D^dag t
+            c1.c = 1.0 / (1.0 + tw * tw);
+            c1.ta = tw;
+        }
+        check(launch_hop(*g, prec, link12, ph, c1, s));
+        const Reduce rr = red(kEpiCgRr);
+        HopCall c2{};
+        c2.gauge = gauge;
+        c2.in[1] = tmp;
+        c2.xs[0] = t;
+        c2.out[0] = q;
+        c2.first_par = 0; c2.npar = 1; c2.dag = true; c2.skip = skip;
+        c2.red = &rr;
+        coef(c2, -1.0, 2);
+        if (tw != 0.0) c2.tx = -tw;
+        c2.cg[0] = x; c2.cg[1] = p; c2.cg[2] = r;
+        check(launch_hop(*g, prec, link12, ph, c2, s));
+        applies += 1;
+    }
+
     void blas(int op, void *v0, void *v1 = nullptr, void *v2 = nullptr, void *v3 = nullptr,
               void *v4 = nullptr, void *v5 = nullptr, int epi = kEpiNone, bool use_skip = true,
               double a = 0.0, double b = 0.0) {
@@ -414,8 +451,7 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
             for (int it = 0; it < m; ++it) {
                 const int *skip = &k.sc->done;
                 k.apply(p, t, false, kEpiCgPap, nullptr, skip);    // t = A p, pap = |t|^2
-                k.apply(t, q, true, kEpiNone, nullptr, skip);      // q = A^dag t
-                k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+                k.cg_step(t, q, x, p, r, skip);                    // q = A^dag t; x, r, rr
                 k.blas(kOpCgP, r, p);
             }
         });
@@ -501,8 +537,7 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
                 for (int it = 0; it < m; ++it) {
                     const int *skip = &k32.sc->done;
                     k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
-                    k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
-                    k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
+                    k32.cg_step(lo.t, lo.q, lo.x, lo.p, lo.r, skip);
                     k32.blas(kOpCgP, lo.r, lo.p);
                 }
             });
@@ -809,13 +844,16 @@ static Cost apply_cost(const Geom &g, int prec, bool link12, bool eo) {
     return {(2 * 1320.0 + 48.0) * V / 2, V / 2 * (2 * (2 * sp + 8 * ln) + sp)};
 }
 
-static Cost iter_cost(const Geom &g, int prec, bool link12, bool eo, bool bicg) {
+static Cost iter_cost(const Geom &g, int prec, bool link12, bool eo, bool bicg,
+                      bool fused = false) {
     const Cost a = apply_cost(g, prec, link12, eo);
     const double Vs = eo ? g.Vh : 2.0 * g.Vh;
     const double sp = site_bytes(prec);
-    // CG: 2 applies + CgXR (4 reads, 2 writes) + CgP (2 reads, 1 write)
-    // BiCGStab: 2 applies (+1 aux read) + BiP (3r 1w) + BiS (2r 1w) + BiXR (5r 2w)
-    const double vec = bicg ? (1 + 4 + 3 + 7) : (6 + 3);
+    // CG: 2 applies + CgXR (4 reads, 2 writes) + CgP (2 reads, 1 write); with
+    // the update fused into the adjoint (Space::cg_step) q is neither written
+    // nor read again. BiCGStab: 2 applies (+1 aux read) + BiP (3r 1w) + BiS
+    // (2r 1w) + BiXR (5r 2w)
+    const double vec = bicg ? (1 + 4 + 3 + 7) : (fused ? 4 + 3 : 6 + 3);
     return {2 * a.flops, 2 * a.bytes + vec * Vs * sp};
 }
 
@@ -962,7 +1000,9 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                     reliable += cr.updates;
                 }
                 total_it += cr.iters;
-                const Cost c = iter_cost(g, lo_iters ? lo : WL_F64, link12, eo, bicg);
+                const int iprec = lo_iters ? lo : WL_F64;
+                const Cost c = iter_cost(g, iprec, link12, eo, bicg,
+                                         !bicg && eo && iprec != WL_F16S);
                 flops += c.flops * cr.iters;
                 bytes += c.bytes * cr.iters;
                 if (eo) eo_reconstruct(k, in.b, in.x);
