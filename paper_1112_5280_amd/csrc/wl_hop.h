@@ -830,8 +830,8 @@ static hipError_t launch_red(const HopArgs<Real<ST>> &a, const HopCall &call, in
     case kRedNone: return launch_t<ST, NCL, DAG, XPAY, kRedNone>(a, call, prec, link12, s);
     case kRedNorm: return launch_t<ST, NCL, DAG, XPAY, kRedNorm>(a, call, prec, link12, s);
     case kRedDotAux: return launch_t<ST, NCL, DAG, XPAY, kRedDotAux>(a, call, prec, link12, s);
-    case kRedCgXR:   // the last hop of an adjoint Schur apply (FP64 or FP32 storage)
-        if constexpr (DAG && XPAY && !std::is_same<ST, Half>::value)
+    case kRedCgXR:   // the last hop of an adjoint Schur apply
+        if constexpr (DAG && XPAY)
             return launch_t<ST, NCL, DAG, XPAY, kRedCgXR>(a, call, prec, link12, s);
         return hipErrorInvalidValue;
     default:

@@ -233,12 +233,16 @@ struct Space {
     }
 
     // The CG step after t = A p: q = A^dag t, x += alpha p, r -= alpha q and
-    // ||r||^2 (kEpiCgRr). For one RHS on the even-odd system in FP64 or FP32
-    // storage the update runs in the epilogue of the adjoint's last hop and q
-    // is never stored (192 B per FP32 site and iteration less); otherwise, and
-    // bitwise alike, as the hop followed by the update pass.
+    // ||r||^2 (kEpiCgRr). On the even-odd system the update runs in the
+    // epilogue of the adjoint's last hop and q is never stored (192 B per FP32
+    // site and iteration less) -- for one RHS, and for batches in FP16
+    // storage (their hops take one RHS per thread). FP64 and FP32 batches, on
+    // register-blocked hops, keep the hop and the update pass, which give the
+    // fused path's bits; in FP16 storage the fused q is not rounded to FP16,
+    // so single and batched FP16 solves both fuse.
+    static bool fuses_cg(bool eo, int nrhs, int prec) { return eo && (nrhs == 1 || prec == WL_F16S); }
     void cg_step(const void *t, void *q, void *x, void *p, void *r, const int *skip) {
-        if (!(eo && nrhs == 1 && !gtab && prec != WL_F16S)) {
+        if (!fuses_cg(eo, nrhs, prec)) {
             apply(t, q, true, kEpiNone, nullptr, skip);
             blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
             return;
@@ -248,6 +252,7 @@ struct Space {
         c1.in[0] = t;
         c1.out[1] = tmp;
         c1.first_par = 1; c1.npar = 1; c1.dag = true; c1.skip = skip;
+        c1.nrhs = nrhs; c1.fstride = fstride;
         coef(c1, 1.0, 0);
         if (tw != 0.0) {   // tmp = A^-dag D^dag t
             c1.c = 1.0 / (1.0 + tw * tw);
@@ -262,6 +267,7 @@ struct Space {
         c2.out[0] = q;
         c2.first_par = 0; c2.npar = 1; c2.dag = true; c2.skip = skip;
         c2.red = &rr;
+        c2.nrhs = nrhs; c2.fstride = fstride;
         coef(c2, -1.0, 2);
         if (tw != 0.0) c2.tx = -tw;
         c2.cg[0] = x; c2.cg[1] = p; c2.cg[2] = r;
@@ -1002,7 +1008,7 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                 total_it += cr.iters;
                 const int iprec = lo_iters ? lo : WL_F64;
                 const Cost c = iter_cost(g, iprec, link12, eo, bicg,
-                                         !bicg && eo && iprec != WL_F16S);
+                                         !bicg && Space::fuses_cg(eo, 1, iprec));
                 flops += c.flops * cr.iters;
                 bytes += c.bytes * cr.iters;
                 if (eo) eo_reconstruct(k, in.b, in.x);
@@ -1143,8 +1149,7 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
             for (int it = 0; it < m; ++it) {
                 const int *skip = &k.sc->done;
                 k.apply(p, t, false, kEpiCgPap, nullptr, skip);
-                k.apply(t, q, true, kEpiNone, nullptr, skip);
-                k.blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
+                k.cg_step(t, q, x, p, r, skip);
                 k.blas(kOpCgP, r, p);
             }
         });
@@ -1236,8 +1241,7 @@ static void cg_reliable_batch(Space &k64, Space &k32, const void *rhs, void *x, 
                 for (int it = 0; it < cnt; ++it) {
                     const int *skip = &k32.sc->done;
                     k32.apply(lo.p, lo.t, false, kEpiCgPap, nullptr, skip);
-                    k32.apply(lo.t, lo.q, true, kEpiNone, nullptr, skip);
-                    k32.blas(kOpCgXR, lo.x, lo.p, lo.r, lo.q, nullptr, nullptr, kEpiCgRr);
+                    k32.cg_step(lo.t, lo.q, lo.x, lo.p, lo.r, skip);
                     k32.blas(kOpCgP, lo.r, lo.p);
                 }
             });
@@ -1387,8 +1391,8 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     double flops = 0, bytes = 0;
     int ret = WL_OK;
     const Cost tr = apply_cost(g, WL_F64, link12, false);
-    const Cost ic = iter_cost(g, (in.flags & WL_MIXED) ? lo_prec(in.flags) : WL_F64, link12, eo,
-                              false);
+    const int iprec = (in.flags & WL_MIXED) ? lo_prec(in.flags) : WL_F64;
+    const Cost ic = iter_cost(g, iprec, link12, eo, false, Space::fuses_cg(eo, nrhs, iprec));
     auto true_res = [&]() {
         full.apply(in.x, v[6], false, kEpiNone, nullptr, nullptr);
         full.blas(kOpXmy, const_cast<void *>(in.b), v[6], nullptr, nullptr, nullptr, nullptr,
