@@ -117,10 +117,8 @@ hipError_t launch_hop(const Geom &g, int prec, bool link12, const Phases &ph,
         if (red == kRedDotAux && !call.aux[call.first_par]) return hipErrorInvalidValue;
         if (red == kRedTS && !call.xs[call.first_par]) return hipErrorInvalidValue;
         if (call.cg[0]) {
-            // one RHS per thread: one field, or FP16 storage (never register-blocked)
             if (call.red->epilogue != kEpiCgRr || !call.red->sc || !call.cg[1] || !call.cg[2] ||
-                call.npar != 1 || (call.nrhs != 1 && prec != WL_F16S) || !call.dag ||
-                !call.xs[call.first_par])
+                call.npar != 1 || !call.dag || !call.xs[call.first_par])
                 return hipErrorInvalidValue;
             red = kRedCgXR;
         }

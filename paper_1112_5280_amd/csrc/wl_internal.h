@@ -356,8 +356,8 @@ struct HopCall {
     int cpow = 0;
     // twisted mass: out = sx (1 + i tx g5) xs + c (1 + i ta g5) D in
     double tx = 0.0, ta = 0.0, sx = 1.0;
-    // fused CG update (one output parity; one RHS, or a batch in FP16 storage;
-    // red with kEpiCgRr): the hop's result q is not stored; the kernel applies
+    // fused CG update (one output parity, red with kEpiCgRr; one RHS per
+    // thread): the hop's result q is not stored; the kernel applies
     // x += alpha p, r -= alpha q and sums ||r||^2 on the blocks cg = {x, p, r}
     // of the output parity (alpha from the RHS's Scalars). `out` stays a valid
     // buffer: the autotuner times candidate launch shapes on the plain

@@ -234,15 +234,13 @@ struct Space {
 
     // The CG step after t = A p: q = A^dag t, x += alpha p, r -= alpha q and
     // ||r||^2 (kEpiCgRr). On the even-odd system the update runs in the
-    // epilogue of the adjoint's last hop and q is never stored (192 B per FP32
-    // site and iteration less) -- for one RHS, and for batches in FP16
-    // storage (their hops take one RHS per thread). FP64 and FP32 batches, on
-    // register-blocked hops, keep the hop and the update pass, which give the
-    // fused path's bits; in FP16 storage the fused q is not rounded to FP16,
-    // so single and batched FP16 solves both fuse.
-    static bool fuses_cg(bool eo, int nrhs, int prec) { return eo && (nrhs == 1 || prec == WL_F16S); }
+    // epilogue of the adjoint's last hop (one RHS per thread, which is also
+    // the tuned shape of batched even-odd hops) and q is never stored: 192 B
+    // per FP32 site and iteration less. The full-lattice system keeps the hop
+    // and the update pass; in FP64 and FP32 both forms give the same bits.
+    static bool fuses_cg(bool eo) { return eo; }
     void cg_step(const void *t, void *q, void *x, void *p, void *r, const int *skip) {
-        if (!fuses_cg(eo, nrhs, prec)) {
+        if (!fuses_cg(eo)) {
             apply(t, q, true, kEpiNone, nullptr, skip);
             blas(kOpCgXR, x, p, r, q, nullptr, nullptr, kEpiCgRr);
             return;
@@ -1008,7 +1006,7 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
                 total_it += cr.iters;
                 const int iprec = lo_iters ? lo : WL_F64;
                 const Cost c = iter_cost(g, iprec, link12, eo, bicg,
-                                         !bicg && Space::fuses_cg(eo, 1, iprec));
+                                         !bicg && Space::fuses_cg(eo));
                 flops += c.flops * cr.iters;
                 bytes += c.bytes * cr.iters;
                 if (eo) eo_reconstruct(k, in.b, in.x);
@@ -1392,7 +1390,7 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
     int ret = WL_OK;
     const Cost tr = apply_cost(g, WL_F64, link12, false);
     const int iprec = (in.flags & WL_MIXED) ? lo_prec(in.flags) : WL_F64;
-    const Cost ic = iter_cost(g, iprec, link12, eo, false, Space::fuses_cg(eo, nrhs, iprec));
+    const Cost ic = iter_cost(g, iprec, link12, eo, false, Space::fuses_cg(eo));
     auto true_res = [&]() {
         full.apply(in.x, v[6], false, kEpiNone, nullptr, nullptr);
         full.blas(kOpXmy, const_cast<void *>(in.b), v[6], nullptr, nullptr, nullptr, nullptr,
