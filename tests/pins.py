@@ -465,6 +465,44 @@ def pin_meson_gauge_invariance(orc, dims=(2, 2, 4, 4)):
     assert rel(orc.meson(props2, dims), orc.meson(props, dims)) < 1e-13
 
 
+def pin_meson_time_reversal(orc, dims=(2, 2, 2, 8), kappa=0.12):
+    """On a time-reversal symmetric field (spatial links equal at t and -t,
+    U_t(x, t) = U_t(x, -t-1)^dag; the antiperiodic wrap maps to itself) the
+    point-source propagator from t = 0 obeys S(-t) = T S(t) T^-1 up to the
+    source's transform, T = g_t g5 (it anticommutes with g_t, commutes with the
+    spatial g_k), so every channel of Eq. 1 is even or odd in t:
+    |C_Gamma(t)| = |C_Gamma(Lt - t)|, the pion (always negative) exactly even.
+    The propagators are the oracle's own CGNR solves."""
+    Lx, Ly, Lz, Lt = dims
+    V = Lx * Ly * Lz * Lt
+    base = synth.gauge_haar(dims, 81).reshape(Lt, Lz, Ly, Lx, 4, 3, 3)
+    U = np.empty_like(base)
+    for t in range(Lt):
+        U[t, ..., :3, :, :] = base[min(t, Lt - t), ..., :3, :, :]
+    for t in range(Lt // 2):
+        U[t, ..., 3, :, :] = base[t, ..., 3, :, :]
+        U[Lt - 1 - t, ..., 3, :, :] = np.conj(np.swapaxes(base[t, ..., 3, :, :], -1, -2))
+    U = U.reshape(V, 4, 3, 3)
+    mirror = [0] + list(range(Lt - 1, 0, -1))
+
+    def correlators(field):
+        props = np.empty((12, V, 4, 3), np.complex128)
+        for j in range(12):
+            x, st = orc.cgnr(field, synth.point_source(dims, 0, j // 3, j % 3), dims, kappa,
+                             tol=1e-13)
+            assert st["status"] == 0, st
+            props[j] = x
+        return orc.meson(props, dims, 0)
+
+    C = correlators(U)
+    assert (C[15].real < 0).all()
+    assert np.abs(C[15] - C[15, mirror]).max() < 1e-10 * np.abs(C[15]).max()
+    assert np.abs(np.abs(C) - np.abs(C[:, mirror])).max() < 1e-10 * np.abs(C).max()
+    # the symmetry is the field's: the unsymmetrised field breaks it
+    C0 = correlators(base.reshape(V, 4, 3, 3))
+    assert np.abs(C0[15] - C0[15, mirror]).max() > 1e-3 * np.abs(C0[15]).max()
+
+
 def pin_philox_known_answers(orc):
     """Philox4x32-10 reproduces the known-answer vectors published with the
     generator (Random123): zero counter and key, all-ones, and the digits of
@@ -584,7 +622,8 @@ ALL_PINS = [
     pin_neumann, pin_free_field_solve, pin_eo_solve_odd_rows, pin_plaquette,
     pin_tm_free_field_spectrum, pin_tm_dense_and_adjoint, pin_tm_solve_lapack,
     pin_tm_schur_block_elimination, pin_meson_pion_and_completeness,
-    pin_meson_gauge_invariance, pin_philox_known_answers, pin_kp_density,
+    pin_meson_gauge_invariance, pin_meson_time_reversal, pin_philox_known_answers,
+    pin_kp_density,
     pin_heatbath_unitary_and_strong_coupling,
     pin_singular_extremes_dense, pin_singular_extremes_free_field,
 ]
