@@ -87,6 +87,12 @@ extern "C" {
                                 it (fewer launch overheads on small
                                 lattices); the solve waits for `stream` to
                                 drain, then runs on a library-owned stream */
+#define WL_CANON      0x200u /* solve_cg, solve_bicgstab and their twisted-
+                                mass forms: gauge, b and x are in the
+                                canonical complex128 layouts (those
+                                wl_pack_gauge / wl_pack_spinor read); the
+                                solve packs them into its workspace and
+                                unpacks x at the end                          */
 
 /* ---- environment ----------------------------------------------------------
  * WL_TUNE=0             no autotuning of launch shapes (see wl_tuning_report)
@@ -198,7 +204,10 @@ int wilson_dslash_eo_tm(const void *gauge, const void *in, void *out,
                         const double phases[8], int32_t out_parity,
                         uint32_t flags, void *stream);
 
-/* Scratch bytes the solvers need for these dims and flags (nrhs = 1). */
+/* Scratch bytes the solvers need for these dims and flags (0 on bad dims; 0
+ * for WL_CANON with nrhs > 1, which the batched solvers do not take). With
+ * WL_CANON (nrhs = 1) it includes the packed copies of the gauge field, b and
+ * x. */
 size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
 
 /* Solve M x = b (paper Sec. 4: the inversion S ~ M^-1 b) to
@@ -222,7 +231,12 @@ size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
  * residuals, and the global reductions.
  * `gauge` is the packed FP64 gauge field (link format per flags); `b` and `x`
  * are packed FP64 full spinors; x is the initial guess with WL_X0, otherwise
- * it is overwritten from zero. `work` is device scratch of at least
+ * it is overwritten from zero. With WL_CANON, `gauge` is the canonical
+ * complex128 field U[V][4][3][3] and `b`, `x` canonical complex128 spinors
+ * psi[V][4][3] (all device memory); the solve packs U (in the link format of
+ * flags), b and, with WL_X0, x into its workspace, solves there, and unpacks
+ * the solution into x -- the same result, bit for bit, as packing them
+ * yourself. `work` is device scratch of at least
  * wl_workspace_bytes(dims, flags, 1) bytes. `stats` (host memory) may be NULL.
  * Blocks until the solve is complete. */
 int solve_cg(const void *gauge, const void *b, void *x, const int32_t dims[4],

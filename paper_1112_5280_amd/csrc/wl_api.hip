@@ -285,10 +285,30 @@ int wilson_dslash_eo_tm(const void *gauge, const void *in, void *out, const int3
     return e == hipSuccess ? WL_OK : hip_fail(e, "wilson_dslash_eo");
 }
 
+// WL_CANON: the packed FP64 gauge field, b and x after the solver's own
+// workspace, each on a 256-byte boundary
+struct CanonStage {
+    size_t gauge, b, x, end;
+};
+static CanonStage canon_stage(const Geom &g, uint32_t flags) {
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    CanonStage c;
+    c.gauge = up(workspace_bytes(g, flags & ~WL_CANON));
+    c.b = c.gauge + up(gauge_bytes(g, WL_F64, flags & WL_LINK12));
+    c.x = c.b + up(2 * spinor_block_bytes(g, WL_F64));
+    c.end = c.x + 2 * spinor_block_bytes(g, WL_F64);
+    return c;
+}
+
+static size_t solve_workspace_bytes(const Geom &g, uint32_t flags) {
+    return (flags & WL_CANON) ? canon_stage(g, flags).end : workspace_bytes(g, flags);
+}
+
 size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs) {
     Geom g;
     std::string why;
     if (!make_geom(dims, &g, &why) || nrhs < 1 || nrhs > kMaxBatch) return 0;
+    if (flags & WL_CANON) return nrhs == 1 ? canon_stage(g, flags).end : 0;
     return nrhs == 1 ? workspace_bytes(g, flags) : workspace_bytes_batch(g, flags, nrhs);
 }
 
@@ -473,6 +493,8 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     if (!make_geom(dims, &in.g, &why) || !get_phases(phases, &in.ph, &why))
         return fail(WL_EINVAL, why);
     if (static_scratch) {
+        if (flags & WL_CANON)
+            return fail(WL_EINVAL, "solve_cg_noalloc takes packed fields (no WL_CANON)");
         if (flags & WL_GRAPH)
             return fail(WL_EINVAL, "solve_cg_noalloc: WL_GRAPH instantiates graphs, which "
                                    "allocates; use solve_cg for graph replay");
@@ -488,7 +510,7 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
         work_bytes = kStaticScratchBytes;
         in.no_alloc = true;
     }
-    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    if (flags & ~(kKnownFlags | WL_CANON)) return fail(WL_EINVAL, "unknown flag bits");
     const uint32_t inner = flags & WL_PREC_MASK;
     if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
         return fail(WL_EINVAL, "solver buffers are FP64; a lower precision (WL_F32, WL_F16S) "
@@ -499,7 +521,7 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     if (!std::isfinite(kappa)) return fail(WL_EINVAL, "kappa is not finite");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(WL_EINVAL, "tol must be positive");
     if (maxiter < 1) return fail(WL_EINVAL, "maxiter must be >= 1");
-    const size_t need = workspace_bytes(in.g, flags);
+    const size_t need = solve_workspace_bytes(in.g, flags);
     if (work_bytes < need)
         return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
                                        " bytes, got " + std::to_string(work_bytes));
@@ -509,15 +531,34 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     in.kappa = kappa;
     in.tol = tol;
     in.maxiter = maxiter;
-    in.flags = flags;
+    in.flags = flags & ~WL_CANON;
     in.work = work;
     in.s = static_cast<hipStream_t>(stream);
+    const hipStream_t caller = in.s;
+    if (flags & WL_CANON) {   // pack into the workspace's staging area
+        const CanonStage c = canon_stage(in.g, flags);
+        char *w = static_cast<char *>(work);
+        hipError_t e = launch_pack_gauge(in.g, WL_F64, flags & WL_LINK12, gauge, w + c.gauge,
+                                         caller);
+        if (e == hipSuccess) e = launch_pack_spinor(in.g, WL_F64, b, w + c.b, caller);
+        if (e == hipSuccess && (flags & WL_X0))
+            e = launch_pack_spinor(in.g, WL_F64, x, w + c.x, caller);
+        if (e != hipSuccess) return hip_fail(e, "packing the canonical fields");
+        in.gauge = w + c.gauge;
+        in.b = w + c.b;
+        in.x = w + c.x;
+    }
     int st;
     if (in.no_alloc) {
         const TuningSuspended no_tuning;   // tuning would create events
         st = run_solver(bicg, in, stats, &why);
     } else {
         st = run_solver(bicg, in, stats, &why);
+    }
+    if ((flags & WL_CANON) && st != WL_EHIP) {   // the solution (or best iterate) back
+        hipError_t e = launch_unpack_spinor(in.g, WL_F64, in.x, x, caller);
+        if (e == hipSuccess) e = hipStreamSynchronize(caller);
+        if (e != hipSuccess) return hip_fail(e, "unpacking the solution");
     }
     if (st != WL_OK) {
         if (why.empty()) {
@@ -653,7 +694,7 @@ int wl_server_create(const wl_server_config *cfg, wl_server **out) {
     if (cfg->merge < 0 || cfg->merge > kMaxBatch) return fail(WL_EINVAL, "merge must be in 0..64");
     if (!get_phases(cfg->phases, &ph, &why)) return fail(WL_EINVAL, why);
     const uint32_t flags = cfg->flags;
-    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
+    if (flags & ~(kKnownFlags | WL_CANON)) return fail(WL_EINVAL, "unknown flag bits");
     const uint32_t inner = flags & WL_PREC_MASK;
     if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
         return fail(WL_EINVAL, "a lower precision (WL_F32, WL_F16S) selects the inner solve of "

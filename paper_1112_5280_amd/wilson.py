@@ -32,6 +32,7 @@ EO = 0x20
 MIXED = 0x40
 X0 = 0x80
 GRAPH = 0x100
+CANON = 0x200   # solvers: canonical complex128 gauge field and spinors (packed inside)
 
 OK, NOCONV, BREAKDOWN, STAGNATED = 0, 1, 2, 3
 EINVAL, EWORKSPACE, EHIP = -1, -2, -3

@@ -192,3 +192,17 @@ def test_host_tensors_are_refused_before_any_call(w):
         w.heatbath(U, (4, 4, 4, 4), 1.0)
     with pytest.raises(ValueError):
         w._ptr(torch.zeros(4))
+
+
+def test_canonical_workspace(w):
+    """WL_CANON adds the packed gauge field, b and x (each on a 256-byte
+    boundary) after the solver's own workspace; batches do not take it."""
+    up = lambda v: (v + 255) // 256 * 256
+    for d in ((4, 4, 4, 4), (6, 4, 6, 10)):
+        for f in (w.EO, w.EO | w.MIXED, w.EO | w.MIXED | w.F16S | w.LINK12):
+            base = w.workspace_bytes(d, f)
+            canon = w.workspace_bytes(d, f | w.CANON)
+            want = up(up(up(base) + w.gauge_bytes(d, f & w.LINK12)) + w.spinor_bytes(d)) + \
+                w.spinor_bytes(d)
+            assert canon == want, (d, f)
+        assert w.workspace_bytes(d, w.EO | w.CANON, 3) == 0
