@@ -700,14 +700,20 @@ def main():
             f = prec | lk
             tm = time_kernel(lambda: w.wilson_dslash(G, P, O, dims, kappa, flags=f, stream=s),
                              n, torch)
+            # beside the algorithmic rate, the paper's no-reuse convention: 8
+            # neighbour spinors and 8 links read and one spinor written per
+            # output site (2880 B for FP64-18), to compare with its 105 GB/s
+            noreuse = 9 * sb + 8 * lb
             variants["M_%s_%s" % (pname, lname)] = {
                 "us": tm * 1e6, "GBs": V * (2 * sb + 4 * lb) / tm / 1e9,
+                "no_reuse_GBs": V * noreuse / tm / 1e9,
                 "GFLOPs": 1368 * V / tm / 1e9}
             te = time_kernel(lambda: w.wilson_dslash_eo(
                 G, w.parity_block(P, dims, prec, 0), Oh, dims, kappa, 1, flags=f | w.HOP,
                 stream=s), n, torch)
             variants["Deo_%s_%s" % (pname, lname)] = {
                 "us": te * 1e6, "GBs": Vh * (2 * sb + 8 * lb) / te / 1e9,
+                "no_reuse_GBs": Vh * noreuse / te / 1e9,
                 "GFLOPs": 1320 * Vh / te / 1e9}
             del G, P, O, Oh
     torch.cuda.empty_cache()
@@ -748,7 +754,8 @@ def main():
                   "kernel": "wl::hop_kernel<double, %d, false, false, 0, 1, true> "
                             "(even-odd hop, FP64)" % (6 if args.link12 else 9),
                   "bytes_per_launch": per64, "avg_us": variants[dom64]["us"],
-                  "gflops": variants[dom64]["GFLOPs"]}
+                  "gflops": variants[dom64]["GFLOPs"],
+                  "no_reuse_GBs": variants[dom64]["no_reuse_GBs"]}
 
     small = None if args.no_small else small_configs(w, torch, synth, args.kernel_launches)
 
@@ -898,7 +905,8 @@ def main():
         "roofline": pick(roofline, "bound", "achieved", "peak", "unit", "frac", "traffic",
                          "kernel", "bytes_per_launch", "avg_us"),
         "roofline_fp64_eo": pick(roofline64, "bound", "achieved", "peak", "unit", "frac",
-                                 "traffic", "kernel", "bytes_per_launch", "avg_us"),
+                                 "traffic", "kernel", "bytes_per_launch", "avg_us", "gflops",
+                                 "no_reuse_GBs"),
         "cpu_baseline": pick(cpu, "value", "unit", "cores", "kind", "sample",
                              "seconds_per_iteration", "seconds_per_apply",
                              "seconds_per_apply_1_core"),
@@ -907,8 +915,9 @@ def main():
     }
     for k in ("roofline", "roofline_fp64_eo"):
         if out[k]:
-            for f in ("achieved", "frac", "avg_us"):
-                out[k][f] = round(out[k][f], 4)
+            for f in ("achieved", "frac", "avg_us", "gflops", "no_reuse_GBs"):
+                if f in out[k]:
+                    out[k][f] = round(out[k][f], 4)
     print(json.dumps(out), flush=True)
     return 0
 
