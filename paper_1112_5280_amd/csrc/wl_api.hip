@@ -555,7 +555,7 @@ static int solve_common(bool bicg, const void *gauge, const void *b, void *x,
     } else {
         st = run_solver(bicg, in, stats, &why);
     }
-    if ((flags & WL_CANON) && st != WL_EHIP) {   // the solution (or best iterate) back
+    if ((flags & WL_CANON) && st >= 0) {   // the solution (or best iterate) back
         hipError_t e = launch_unpack_spinor(in.g, WL_F64, in.x, x, caller);
         if (e == hipSuccess) e = hipStreamSynchronize(caller);
         if (e != hipSuccess) return hip_fail(e, "unpacking the solution");

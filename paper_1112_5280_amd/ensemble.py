@@ -51,6 +51,9 @@ class Ensemble:
                                  dtype=torch.uint8, device=dev)
         self.gen = torch.cuda.Stream()
         self.meas = torch.cuda.Stream() if overlap else self.gen
+        # the buffers above were filled on the current stream
+        self.gen.wait_stream(torch.cuda.current_stream())
+        self.meas.wait_stream(torch.cuda.current_stream())
         self.sweep = 0
         self.stats = []
 

@@ -191,9 +191,21 @@ def _ptr(t):
     return ctypes.c_void_p(int(t))
 
 
-def _stream(stream):
+def _stream(stream, *keep):
+    """The HIP stream of a library call: the current stream, or `stream`. A
+    call on another stream than the current one is first ordered after the
+    work already queued on the current stream (the producers of its inputs,
+    and the last users of the memory the caching allocator just handed this
+    binding there); the tensors in `keep`, allocated here, stay reserved until
+    `stream` has passed the call."""
+    cur = torch.cuda.current_stream()
     if stream is None:
-        stream = torch.cuda.current_stream()
+        return ctypes.c_void_p(cur.cuda_stream)
+    if stream != cur:
+        stream.wait_stream(cur)
+        for t in keep:
+            if t is not None:
+                t.record_stream(stream)
     return ctypes.c_void_p(stream.cuda_stream)
 
 
@@ -258,7 +270,7 @@ def pack_gauge(U, dims, flags=F64, out=None, stream=None, device="cuda"):
     Ud = _canon_device(U, (V, 4, 3, 3), device)
     if out is None:
         out = torch.empty(gauge_bytes(dims, flags), dtype=torch.uint8, device=device)
-    _check(lib.wl_pack_gauge(_ptr(Ud), _ptr(out), _dims(dims), flags, _stream(stream)),
+    _check(lib.wl_pack_gauge(_ptr(Ud), _ptr(out), _dims(dims), flags, _stream(stream, Ud, out)),
            "wl_pack_gauge")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return out
@@ -270,7 +282,7 @@ def pack_spinor(psi, dims, flags=F64, out=None, stream=None, device="cuda"):
     pd = _canon_device(psi, (V, 4, 3), device)
     if out is None:
         out = torch.empty(spinor_bytes(dims, flags, 2), dtype=torch.uint8, device=device)
-    _check(lib.wl_pack_spinor(_ptr(pd), _ptr(out), _dims(dims), flags, _stream(stream)),
+    _check(lib.wl_pack_spinor(_ptr(pd), _ptr(out), _dims(dims), flags, _stream(stream, pd, out)),
            "wl_pack_spinor")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return out
@@ -281,7 +293,7 @@ def unpack_spinor(packed, dims, flags=F64, stream=None):
     V = int(np.prod(dims))
     out = torch.empty((V, 4, 3), dtype=torch.complex128, device=packed.device)
     _check(lib.wl_unpack_spinor(_ptr(packed), _ptr(out), _dims(dims), flags,
-                                _stream(stream)), "wl_unpack_spinor")
+                                _stream(stream, out)), "wl_unpack_spinor")
     return out
 
 
@@ -312,7 +324,7 @@ def _solve(fn, name, gauge, b, x, dims, kappa, phases, tol, maxiter, flags, work
     extra = () if mu is None else (float(mu),)
     code = fn(_ptr(gauge), _ptr(b), _ptr(x), _dims(dims), float(kappa), *extra, _phases(phases),
               float(tol), int(maxiter), flags, _ptr(work), work.numel(), ctypes.byref(st),
-              _stream(stream))
+              _stream(stream, work))
     _check(code, name)
     d = st.as_dict()
     d["status_name"] = STATUS_NAMES.get(code, "?")
@@ -393,11 +405,8 @@ def meson_correlators(props, dims, t0=0, work=None, stream=None):
         work = torch.empty(max(int(lib.wl_meson_workspace_bytes(_dims(dims))), 1),
                            dtype=torch.uint8, device=props.device)
     _check(lib.wl_meson_correlators(_ptr(props), _dims(dims), int(t0), _ptr(corr), _ptr(work),
-                                    work.numel(), _stream(stream)), "wl_meson_correlators")
-    if stream is not None:
-        # both were allocated on the current stream; the kernel runs on `stream`
-        corr.record_stream(stream)
-        work.record_stream(stream)
+                                    work.numel(), _stream(stream, corr, work)),
+           "wl_meson_correlators")
     return torch.view_as_complex(corr)
 
 
@@ -419,7 +428,7 @@ def plaquette(U, dims, stream=None):
     work = torch.empty(max(int(lib.wl_plaquette_workspace_bytes(_dims(dims))), 8),
                        dtype=torch.uint8, device=U.device)
     _check(lib.wl_plaquette(_ptr(U), _dims(dims), _ptr(out), _ptr(work), work.numel(),
-                            _stream(stream)), "wl_plaquette")
+                            _stream(stream, out, work)), "wl_plaquette")
     (torch.cuda.current_stream() if stream is None else stream).synchronize()
     return float(out.cpu())
 
@@ -452,7 +461,7 @@ def solve_cg_batch(gauge, b, x, nrhs, dims, kappa, phases=ANTIPERIODIC_T, tol=1e
     st = (SolveStats * int(nrhs))()
     code = lib.solve_cg_batch(_ptr(gauge), _ptr(b), _ptr(x), int(nrhs), _dims(dims),
                               float(kappa), _phases(phases), float(tol), int(maxiter), flags,
-                              _ptr(work), work.numel(), st, _stream(stream))
+                              _ptr(work), work.numel(), st, _stream(stream, work))
     _check(code, "solve_cg_batch")
     out = []
     for s in st:
@@ -506,7 +515,7 @@ def solve_cg_problems(problems, phases=ANTIPERIODIC_T, tol=1e-10, maxiter=100000
         work = torch.empty(max(need, 1), dtype=torch.uint8, device=problems[0].b.device)
     st = (SolveStats * n)()
     code = lib.solve_cg_problems(arr, n, _phases(phases), float(tol), int(maxiter), flags,
-                                 _ptr(work), work.numel(), st, _stream(stream))
+                                 _ptr(work), work.numel(), st, _stream(stream, work))
     _check(code, "solve_cg_problems")
     out = []
     for s in st:
