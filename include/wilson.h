@@ -404,9 +404,14 @@ size_t wl_tuning_report(char *buf, size_t len);
  * its lattice and the server's flags) is carved; gauge fields, sources and
  * solutions stay caller-owned device memory (gauge fields are typically kept
  * resident and shared by many requests) and must stay valid until the request
- * is collected. Requests are admitted first-in first-out: the oldest waiting
- * request starts as soon as a slot is idle and its workspace fits in the free
- * arena; each slot is a host thread with its own stream, so the solves of all
+ * is collected. Requests are admitted earliest deadline first, the deadline
+ * of a request being its submission time plus `site_slack` seconds per site
+ * of its lattice (site_slack = 0: first-in first-out): that request starts as
+ * soon as a slot is idle and its workspace fits in the free arena, and the
+ * requests behind it wait until then. A positive site_slack lets small
+ * lattices overtake large ones submitted at most site_slack * (V_large -
+ * V_small) seconds earlier, so a large request is passed over for a bounded
+ * time. Each slot is a host thread with its own stream, so the solves of all
  * admitted requests overlap on the device. With `merge` > 1 the slot also
  * takes up to merge - 1 further waiting requests of the same lattice size, if
  * that lattice has at most 131072 sites (a larger solve fills the device by
@@ -428,6 +433,8 @@ typedef struct {
     double phases[8];     /* boundary phases, as for wilson_dslash               */
     int32_t merge;        /* most requests of one size solved as one batch,    */
                           /* 0..64 (0 or 1: every request alone)                */
+    double site_slack;    /* admission deadline = submission + site_slack * V  */
+                          /* seconds, V the lattice's sites; >= 0 (0: FIFO)     */
 } wl_server_config;
 
 /* Timestamps of one request, seconds since the server was created. */

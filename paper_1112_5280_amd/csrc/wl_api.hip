@@ -693,8 +693,11 @@ int wl_server_create(const wl_server_config *cfg, wl_server **out) {
     if (cfg->slots < 1 || cfg->slots > 64) return fail(WL_EINVAL, "slots must be in 1..64");
     if (cfg->merge < 0 || cfg->merge > kMaxBatch) return fail(WL_EINVAL, "merge must be in 0..64");
     if (!get_phases(cfg->phases, &ph, &why)) return fail(WL_EINVAL, why);
+    if (!(cfg->site_slack >= 0.0) || !std::isfinite(cfg->site_slack))
+        return fail(WL_EINVAL, "site_slack must be finite and >= 0");
     const uint32_t flags = cfg->flags;
-    if (flags & ~(kKnownFlags | WL_CANON)) return fail(WL_EINVAL, "unknown flag bits");
+    if (flags & WL_CANON) return fail(WL_EINVAL, "the server takes packed fields (no WL_CANON)");
+    if (flags & ~kKnownFlags) return fail(WL_EINVAL, "unknown flag bits");
     const uint32_t inner = flags & WL_PREC_MASK;
     if (inner == WL_PREC_MASK || (inner != WL_F64 && !(flags & WL_MIXED)))
         return fail(WL_EINVAL, "a lower precision (WL_F32, WL_F16S) selects the inner solve of "

@@ -1,10 +1,12 @@
 // wl_server.hip -- the solve server behind wl_server_* (include/wilson.h).
 //
-// Requests (one lattice problem each) wait in a FIFO. A fixed set of slots,
-// each a host thread with its own non-blocking stream, takes the oldest
-// request as soon as the slot is idle and the request's solver workspace fits
-// in the free part of the server's device arena; the solve then runs on the
-// slot's stream, overlapping on the device with every other admitted solve.
+// Requests (one lattice problem each) wait in a queue. A fixed set of slots,
+// each a host thread with its own non-blocking stream, takes the waiting
+// request with the earliest deadline -- submission time plus site_slack
+// seconds per lattice site, so with site_slack = 0 the oldest -- as soon as
+// the slot is idle and that request's solver workspace fits in the free part
+// of the server's device arena; the solve then runs on the slot's stream,
+// overlapping on the device with every other admitted solve.
 // When it finishes, its workspace returns to the arena and the next request
 // is admitted. The arena is one device allocation made at creation and
 // carved by a first-fit allocator with coalescing, so admission by memory is
@@ -109,13 +111,30 @@ struct wl_server {
 
     std::mutex m;
     std::condition_variable cv_admit, cv_done;
-    std::deque<Request *> queue;                       // waiting, oldest first
+    std::deque<Request *> queue;                       // waiting, in submission order
     std::unordered_map<uint64_t, Request *> live;      // every uncollected request
     std::deque<Request *> finished;                    // finished, not collected
     uint64_t next_ticket = 1;
     bool stopping = false;
 
-    bool head_fits() const { return !queue.empty() && arena.can_alloc(queue.front()->ws_bytes); }
+    // admission deadline: a lattice of V sites may be passed over by requests
+    // submitted up to site_slack * V seconds after it (earliest deadline first
+    // keeps small solves from queueing behind large ones, and a large one
+    // waits at most that long for the smaller ones that overtake it)
+    double deadline(const Request *r) const {
+        return r->t.submitted + cfg.site_slack * double(2L * r->g.Vh);
+    }
+    // queue position of the next request to admit: the earliest deadline, the
+    // earliest submission among equal deadlines
+    size_t head() const {
+        size_t b = 0;
+        for (size_t j = 1; j < queue.size(); ++j)
+            if (deadline(queue[j]) < deadline(queue[b])) b = j;
+        return b;
+    }
+    bool head_fits() const {
+        return !queue.empty() && arena.can_alloc(queue[head()]->ws_bytes);
+    }
 
     // bytes of a merged batch of m requests of geometry g (one request: the
     // solo solver's workspace), rounded to the arena's alignment
@@ -125,14 +144,16 @@ struct wl_server {
     }
 
     // the head request and, with merging, the waiting requests of its lattice
-    // size (oldest first) that fit beside it; removes them from the queue
-    // and carves their workspace (lock held, head_fits() true)
+    // size that fit beside it (in submission order, which for one size is
+    // deadline order, so all of them come after the head); removes them from
+    // the queue and carves their workspace (lock held, head_fits() true)
     std::vector<Request *> take_batch(size_t *off, size_t *bytes) {
-        std::vector<Request *> grp{queue.front()};
-        size_t need = queue.front()->ws_bytes;
+        const size_t h = head();
+        std::vector<Request *> grp{queue[h]};
+        size_t need = queue[h]->ws_bytes;
         if (cfg.merge > 1 && 2L * grp[0]->g.Vh <= kMergeMaxSites) {
             const Geom &g = grp[0]->g;
-            for (size_t j = 1; j < queue.size() && int(grp.size()) < cfg.merge; ++j) {
+            for (size_t j = h + 1; j < queue.size() && int(grp.size()) < cfg.merge; ++j) {
                 Request *q = queue[j];
                 if (std::memcmp(q->p.dims, grp[0]->p.dims, sizeof(q->p.dims)) != 0) continue;
                 const size_t more = batch_bytes(g, int(grp.size()) + 1);

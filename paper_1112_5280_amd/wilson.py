@@ -76,7 +76,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("slots", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("tol", ctypes.c_double),
                 ("maxiter", ctypes.c_int32), ("phases", ctypes.c_double * 8),
-                ("merge", ctypes.c_int32)]
+                ("merge", ctypes.c_int32), ("site_slack", ctypes.c_double)]
 
 
 class RequestTimes(ctypes.Structure):
@@ -541,18 +541,21 @@ def tuning_report():
 
 class Server:
     """A solve server (wl_server_*): requests of any lattice size are admitted
-    first-in first-out as solve slots and HBM-budget memory free up, and the
-    admitted solves run concurrently, one stream per slot. With merge > 1 a
-    slot also takes up to merge - 1 more waiting requests of the same lattice
-    size and solves them as one batch (results bitwise those of solo solves).
+    as solve slots and HBM-budget memory free up, earliest deadline first (the
+    deadline: submission time plus site_slack seconds per lattice site; 0 is
+    first-in first-out), and the admitted solves run concurrently, one stream
+    per slot. With merge > 1 a slot also takes up to merge - 1 more waiting
+    requests of the same lattice size and solves them as one batch (results
+    bitwise those of solo solves).
 
     The caller keeps each request's gauge, b and x tensors alive until the
     request is collected with wait() or next()."""
 
     def __init__(self, hbm_budget, slots=4, flags=EO | MIXED, tol=1e-10, maxiter=100000,
-                 phases=ANTIPERIODIC_T, merge=1):
+                 phases=ANTIPERIODIC_T, merge=1, site_slack=0.0):
         cfg = ServerConfig()
         cfg.merge = int(merge)
+        cfg.site_slack = float(site_slack)
         cfg.hbm_budget = int(hbm_budget)
         cfg.slots = int(slots)
         cfg.flags = int(flags)

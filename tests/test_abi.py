@@ -132,6 +132,7 @@ def test_server_config_checks(w):
         c.maxiter = k.get("maxiter", 1000)
         c.phases = w._phases(k.get("phases", w.ANTIPERIODIC_T))
         c.merge = k.get("merge", 1)
+        c.site_slack = k.get("site_slack", 0.0)
         return c
     h = ctypes.c_void_p()
     create = lambda **k: w.lib.wl_server_create(ctypes.byref(cfg(**k)), ctypes.byref(h))
@@ -143,6 +144,9 @@ def test_server_config_checks(w):
     assert create(tol=0.0) == -1
     assert create(maxiter=0) == -1
     assert create(phases=(1, 1, 1, 2)) == -1
+    assert create(site_slack=-1e-9) == -1 and "site_slack" in w.last_error()
+    assert create(site_slack=float("nan")) == -1 and create(site_slack=float("inf")) == -1
+    assert create(flags=w.EO | w.CANON) == -1 and "packed" in w.last_error()
     assert w.lib.wl_server_create(None, ctypes.byref(h)) == -1
     assert h.value is None
     # calls on no server fail cleanly

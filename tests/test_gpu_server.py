@@ -198,3 +198,33 @@ def test_merged_batch_with_initial_guess(w, fields):
         assert code == 0
         x = gu.to_np(w.unpack_spinor(p.x, dims))
         assert oracle.true_residual(U, b, x, dims, 0.14) <= 1e-10
+
+
+def test_admission_earliest_deadline_first(w, fields):
+    """One slot; two 16^4 requests and then three 4^3x8 ones are queued at once.
+    First in, first out (site_slack 0) admits the second 16^4 before the small
+    ones; with a slack of 1 s per site the small lattices' deadlines come
+    first and they overtake it. The order changes no result: every x is
+    bitwise the same in both runs and meets the bound."""
+    flags = 0x20 | 0x40
+    big, small = (16, 16, 16, 16), (4, 4, 4, 8)
+    plan = [big, big, small, small, small]
+    srcs = [synth.gaussian_spinor(d, 700 + i) for i, d in enumerate(plan)]
+    xs = {}
+    for slack in (0.0, 1.0):
+        ps = [w.Problem(d, 0.13, fields[d][1], w.pack_spinor(b, d), w.zeros_spinor(d))
+              for d, b in zip(plan, srcs)]
+        with w.Server(hbm_budget=4 << 30, slots=1, flags=flags, site_slack=slack) as srv:
+            res = [srv.wait(t) for t in [srv.submit(p) for p in ps]]
+        adm = [tm["admitted"] for _, _, tm in res]
+        assert all(code == 0 for code, _, _ in res)
+        if slack == 0.0:
+            assert adm == sorted(adm) and adm[1] <= min(adm[2:]), adm
+        else:
+            assert max(adm[2:]) <= adm[1], adm
+        xs[slack] = [p.x.clone() for p in ps]
+        for d, b, p in zip(plan, srcs, ps):
+            x = gu.to_np(w.unpack_spinor(p.x, d))
+            assert oracle.true_residual(fields[d][0], b, x, d, 0.13) <= 1e-10
+    for a, b in zip(xs[0.0], xs[1.0]):
+        assert torch.equal(a, b)
