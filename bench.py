@@ -249,7 +249,8 @@ def pure_gauge(w, torch, synth, np, U_host, dims, n_launch):
            "heatbath_ms_per_sweep": th * 1e3,
            "link_updates_per_s": 4 * V / th,
            "heatbath_note": "one sweep = 8 launches (4 directions x 2 parities), each link "
-                            "3 SU(2) subgroup draws (Kennedy-Pendleton) from its 6 staples"}
+                            "3 SU(2) subgroup draws (Kennedy-Pendleton for alpha >= 1, unit-disk "
+                            "rejection below) from its 6 staples"}
     out_d = torch.empty(1, dtype=torch.float64, device="cuda")
     pw = torch.empty(max(int(w.lib.wl_plaquette_workspace_bytes(w._dims(dims))), 8),
                      dtype=torch.uint8, device="cuda")
