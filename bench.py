@@ -391,6 +391,34 @@ def small_configs(w, torch, synth, n_launch):
                         "true_res": st["true_res"]}
     out["16^3x32"] = {"lattice": list(dims), "kappa": kappa, "cache_resident": True,
                       "operators": ops, "solves": solves}
+
+    # one GPU's share of 32^3x64 cut into 8 along t: the 32^3x8 local volume
+    # (periodic here; over 8 GPUs its two t faces, one spin-projected half
+    # spinor of 6 complex per face site each, come from the neighbours)
+    dims, kappa = (32, 32, 32, 8), 0.155
+    V = synth.volume(dims)
+    U = synth.gauge_smooth(dims, 0.35, 0)
+    b = synth.gaussian_spinor(dims, 1)
+    face = dims[0] * dims[1] * dims[2]
+    loc = {"lattice": list(dims), "face_sites": face}
+    for prec, pname in ((w.F64, "f64"), (w.F32, "f32")):
+        G = w.pack_gauge(U, dims, prec)
+        P = w.pack_spinor(b, dims, prec)
+        O = w.empty_spinor(dims, prec)
+        Oh = w.empty_spinor(dims, prec, 1)
+        lb = 9 * COMPLEX_BYTES[prec]
+        tm = time_kernel(lambda: w.wilson_dslash(G, P, O, dims, kappa, flags=prec, stream=s),
+                         n_launch, torch)
+        te = time_kernel(lambda: w.wilson_dslash_eo(G, w.parity_block(P, dims, prec, 0), Oh,
+                                                    dims, kappa, 1, flags=prec | w.HOP,
+                                                    stream=s), n_launch, torch)
+        loc["M_%s_18" % pname] = {"us": tm * 1e6,
+                                  "GBs": (2 * SPINOR_BYTES[prec] + 4 * lb) * V / tm / 1e9}
+        loc["Deo_%s_18" % pname] = {"us": te * 1e6,
+                                    "GBs": (2 * SPINOR_BYTES[prec] + 8 * lb) * V / 2 / te / 1e9}
+        loc["face_bytes_%s" % pname] = 6 * COMPLEX_BYTES[prec] * face
+        del G, P, O, Oh
+    out["32^3x8_local_volume"] = loc
     return out
 
 
