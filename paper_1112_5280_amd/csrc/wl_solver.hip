@@ -304,6 +304,27 @@ struct Space {
 // large enough to hide the readback.
 static int chunk_for(const Geom &g) { return g.Vh >= (1 << 18) ? 4 : 16; }
 
+// Iterations still needed to bring ||r||^2 from h.rr down to h.target at the
+// rate of the last `done` iterations (which started from rr_before); -1 when
+// there is no estimate (no progress measured, or the target already met).
+static double cg_need(double rr_before, int done, const Scalars &h) {
+    if (done <= 0 || !(h.target > 0.0) || !(h.rr > h.target) || !(rr_before > h.rr)) return -1.0;
+    return std::log(h.target / h.rr) / (std::log(h.rr / rr_before) / done);
+}
+
+// Length of the next chunk of CG iterations: the estimate above plus one,
+// rounded up to a multiple of 4 (few distinct graph lengths), at most the
+// lattice's chunk. CG does not converge at a fixed rate, so a short estimate
+// costs one more chunk and a long one runs iterations the device skips once
+// the target is met; the arithmetic is the same either way, and on small
+// lattices, where every launch costs more than its work, the trailing
+// skipped launches of a full chunk are saved.
+static int next_chunk(int cmax, double need) {
+    if (!(need >= 0.0) || !(need < cmax)) return cmax;
+    const int n = int(std::ceil(need)) + 1;
+    return std::min(cmax, (n + 3) / 4 * 4);
+}
+
 // ---------------------------------------------------------------------------
 // Chunks of Krylov iterations, enqueued directly or -- with WL_GRAPH --
 // captured into a HIP graph and replayed. A chunk holds kernel launches only
@@ -449,8 +470,11 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
     int done_it = 0;
     Scalars h = read_scalars(k.sc, k.s);
     ChunkRunner runner(k.s, k.graph, chunk_key(1, k, {x, r, p, t, q}));
+    int len = chunk;
     while (!h.done && done_it < maxit) {
-        const int n = std::min(chunk, maxit - done_it);
+        const int n = std::min(len, maxit - done_it);
+        const double rr0 = h.rr;
+        const int it0 = h.iter;
         runner.run(n, [&](int m) {
             for (int it = 0; it < m; ++it) {
                 const int *skip = &k.sc->done;
@@ -461,6 +485,7 @@ static CoreResult cg_core(Space &k, const void *rhs, void *x, void *r, void *p, 
         });
         h = read_scalars(k.sc, k.s);
         done_it = h.iter;
+        len = next_chunk(chunk, cg_need(rr0, h.iter - it0, h));
     }
     CoreResult res;
     res.iters = h.iter;
@@ -535,8 +560,11 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
         Scalars h = read_scalars(k32.sc, k32.s);
         double best = h.rr;
         int best_it = h.iter;
+        int len = chunk;
         while (!h.done && its + h.iter < maxit) {
-            const int n = std::min(chunk, maxit - its - h.iter);
+            const int n = std::min(len, maxit - its - h.iter);
+            const double rr0 = h.rr;
+            const int it0 = h.iter;
             runner.run(n, [&](int m) {
                 for (int it = 0; it < m; ++it) {
                     const int *skip = &k32.sc->done;
@@ -546,6 +574,7 @@ static CoreResult cg_reliable(Space &k64, Space &k32, const void *rhs, void *x, 
                 }
             });
             h = read_scalars(k32.sc, k32.s);
+            len = next_chunk(chunk, cg_need(rr0, h.iter - it0, h));
             if (h.rr < 0.5 * best) {
                 best = h.rr;
                 best_it = h.iter;
@@ -1066,7 +1095,7 @@ int run_solver(bool bicg, const SolveIn &in0, wl_solve_stats *st, std::string *w
         check(hipStreamSynchronize(in.s));
     } catch (const Fail &f) {
         *why = std::string("HIP error in solver: ") + hipGetErrorString(f.err);
-        hipStreamSynchronize(in.s);
+        (void)hipStreamSynchronize(in.s);   // drain; the first error is the one reported
         status = WL_EHIP;
     }
     const auto t1 = std::chrono::steady_clock::now();
@@ -1141,8 +1170,15 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
     };
     int done_it = 0;
     ChunkRunner runner(k.s, k.graph, chunk_key(5, k, {x, r, p, t, q}));
+    int len = chunk;
+    double rr0[kMaxBatch];
+    int it0[kMaxBatch];
     while (!all_done() && done_it < maxit) {
-        const int n = std::min(chunk, maxit - done_it);
+        const int n = std::min(len, maxit - done_it);
+        for (int i = 0; i < k.nrhs; ++i) {
+            rr0[i] = h[i].rr;
+            it0[i] = h[i].iter;
+        }
         runner.run(n, [&](int m) {
             for (int it = 0; it < m; ++it) {
                 const int *skip = &k.sc->done;
@@ -1153,6 +1189,19 @@ static void cg_core_batch(Space &k, const void *rhs, void *x, void *r, void *p, 
         });
         done_it += n;
         read_scalars_n(k.sc, k.nrhs, k.s, h);
+        // the slowest unconverged RHS sets the next chunk (a full one when
+        // any of them has no estimate)
+        double need = 0.0;
+        for (int i = 0; i < k.nrhs; ++i) {
+            if (h[i].done) continue;
+            const double ni = cg_need(rr0[i], h[i].iter - it0[i], h[i]);
+            if (ni < 0.0) {
+                need = -1.0;
+                break;
+            }
+            need = std::max(need, ni);
+        }
+        len = next_chunk(chunk, need);
     }
     for (int i = 0; i < k.nrhs; ++i) iters[i] = h[i].iter;
 }
@@ -1227,14 +1276,21 @@ static void cg_reliable_batch(Space &k64, Space &k32, const void *rhs, void *x, 
             best_it[r] = h[r].iter;
             stopped[r] = 0;
         }
+        int len = chunk;
         while (true) {
             int m = 0;
             for (int r = 0; r < n; ++r)
                 if (running(r)) m = std::max(m, 1);
             if (!m) break;
-            int steps = chunk;
+            int steps = len;
             for (int r = 0; r < n; ++r)
                 if (running(r)) steps = std::min(steps, maxit - its[r] - h[r].iter);
+            double rr0[kMaxBatch];
+            int it0[kMaxBatch];
+            for (int r = 0; r < n; ++r) {
+                rr0[r] = h[r].rr;
+                it0[r] = h[r].iter;
+            }
             runner.run(steps, [&](int cnt) {
                 for (int it = 0; it < cnt; ++it) {
                     const int *skip = &k32.sc->done;
@@ -1261,6 +1317,18 @@ static void cg_reliable_batch(Space &k64, Space &k32, const void *rhs, void *x, 
             }
             for (int r = 0; r < n; ++r)
                 if (stopped[r]) h[r].done = 1;   // mirrors the device flag just set
+            // the next chunk: as in cg_core_batch, for the RHS still iterating
+            double need = 0.0;
+            for (int r = 0; r < n; ++r) {
+                if (!running(r)) continue;
+                const double nr = cg_need(rr0[r], h[r].iter - it0[r], h[r]);
+                if (nr < 0.0) {
+                    need = -1.0;
+                    break;
+                }
+                need = std::max(need, nr);
+            }
+            len = next_chunk(chunk, need);
         }
         // reliable update of every RHS that iterated in this cycle
         for (int r = 0; r < n; ++r) {
@@ -1488,7 +1556,7 @@ int run_cg_batch(const SolveIn &in0, int nrhs, wl_solve_stats *st, std::string *
         check(hipStreamSynchronize(in.s));
     } catch (const Fail &f) {
         *why = std::string("HIP error in solver: ") + hipGetErrorString(f.err);
-        hipStreamSynchronize(in.s);
+        (void)hipStreamSynchronize(in.s);   // drain; the first error is the one reported
         for (int r = 0; r < nrhs; ++r) status[r] = WL_EHIP;
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
