@@ -228,7 +228,8 @@ def batch12(w, torch, synth, n_launch):
 
 
 def pure_gauge(w, torch, synth, np, U_host, dims, n_launch):
-    """The heat bath and the plaquette on the bench lattice, and the chain of
+    """The heat bath and the plaquette on the bench lattice (canonical and
+    packed fields), and the chain of
     configurations with overlapped measurement (paper Sec. 3 and Sec. 4):
     heat-bath sweep time, link updates per second, plaquette kernel time, and
     the seconds per configuration of a 16^3 x 32 chain (2 sweeps per
@@ -259,7 +260,22 @@ def pure_gauge(w, torch, synth, np, U_host, dims, n_launch):
                      n_launch, torch)
     out.update({"plaquette": w.plaquette(U, dims), "plaquette_us": tp * 1e6,
                 "plaquette_GBs": 4 * V * 144 / tp / 1e9})
-    del U, pw
+    # the same two on the packed FP64 field (coalesced loads; the heat bath is
+    # bitwise the canonical one)
+    G = w.pack_gauge(U, dims)
+
+    def one_sweep_packed():
+        w.heatbath_packed(G, dims, 5.7, nsweeps=1, sweep0=sweep[0], seed=11, stream=s)
+        sweep[0] += 1
+    thp = time_kernel(one_sweep_packed, max(2, n_launch // 10), torch)
+    tpp = time_kernel(lambda: w.lib.wl_plaquette_packed(w._ptr(G), w._dims(dims), w._ptr(out_d),
+                                                        w._ptr(pw), pw.numel(), w._stream(s)),
+                      n_launch, torch)
+    out.update({"heatbath_packed_ms_per_sweep": thp * 1e3,
+                "link_updates_per_s_packed": 4 * V / thp,
+                "plaquette_packed_us": tpp * 1e6,
+                "plaquette_packed_GBs": 4 * V * 144 / tpp / 1e9})
+    del U, G, pw
     torch.cuda.empty_cache()
     d2 = (16, 16, 16, 32)
     U0 = synth.gauge_unit(d2)

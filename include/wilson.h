@@ -376,6 +376,20 @@ size_t wl_plaquette_workspace_bytes(const int32_t dims[4]);
 int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *work,
                  size_t work_bytes, void *stream);
 
+/* The same two on the PACKED FP64 18-real gauge field (what wl_pack_gauge
+ * writes with WL_F64 and 18-real links, wl_gauge_bytes(dims, WL_F64) bytes),
+ * whose loads are coalesced: wl_heatbath_packed performs the same
+ * arithmetic on the same links and draws as wl_heatbath, so packing the
+ * canonical field after wl_heatbath gives bitwise the field wl_heatbath_packed
+ * leaves; the solvers take that field as it is, so a chain of configurations
+ * needs no packing between the update and the measurement. wl_plaquette_packed
+ * sums the sites in checkerboard order (the last bits may differ from
+ * wl_plaquette). Same arguments, errors and asynchrony as above. */
+int wl_heatbath_packed(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
+                       uint32_t sweep0, uint32_t seed, void *stream);
+int wl_plaquette_packed(const void *gauge, const int32_t dims[4], double *out, void *work,
+                        size_t work_bytes, void *stream);
+
 /* Streaming device-to-device copy of `bytes` bytes (both pointers 16-byte
  * aligned, bytes a multiple of 16; the buffers must not overlap), loads then
  * non-temporal stores, 64 bytes per thread: the achievable-bandwidth

@@ -631,17 +631,27 @@ int wl_meson_correlators(const void *props, const int32_t dims[4], int32_t t0, d
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_meson_correlators");
 }
 
-int wl_heatbath(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
-                uint32_t sweep0, uint32_t seed, void *stream) {
+static int heatbath_common(void *gauge, bool packed, const int32_t dims[4], double beta,
+                           int32_t nsweeps, uint32_t sweep0, uint32_t seed, void *stream) {
     Geom g;
     std::string why;
     if (!make_geom(dims, &g, &why)) return fail(WL_EINVAL, why);
     if (!gauge) return fail(WL_EINVAL, "NULL buffer");
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(WL_EINVAL, "beta must be positive");
     if (nsweeps < 0) return fail(WL_EINVAL, "nsweeps must be >= 0");
-    const hipError_t e = launch_heatbath(g, gauge, beta, nsweeps, sweep0, seed,
+    const hipError_t e = launch_heatbath(g, gauge, packed, beta, nsweeps, sweep0, seed,
                                          static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_heatbath");
+    return e == hipSuccess ? WL_OK : hip_fail(e, packed ? "wl_heatbath_packed" : "wl_heatbath");
+}
+
+int wl_heatbath(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
+                uint32_t sweep0, uint32_t seed, void *stream) {
+    return heatbath_common(gauge, false, dims, beta, nsweeps, sweep0, seed, stream);
+}
+
+int wl_heatbath_packed(void *gauge, const int32_t dims[4], double beta, int32_t nsweeps,
+                       uint32_t sweep0, uint32_t seed, void *stream) {
+    return heatbath_common(gauge, true, dims, beta, nsweeps, sweep0, seed, stream);
 }
 
 size_t wl_plaquette_workspace_bytes(const int32_t dims[4]) {
@@ -651,8 +661,8 @@ size_t wl_plaquette_workspace_bytes(const int32_t dims[4]) {
     return plaquette_workspace_bytes(g);
 }
 
-int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *work,
-                 size_t work_bytes, void *stream) {
+static int plaquette_common(const void *gauge, bool packed, const int32_t dims[4],
+                            double *out, void *work, size_t work_bytes, void *stream) {
     Geom g;
     std::string why;
     if (!make_geom(dims, &g, &why)) return fail(WL_EINVAL, why);
@@ -661,8 +671,19 @@ int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *wo
     if (work_bytes < need)
         return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
                                        " bytes, got " + std::to_string(work_bytes));
-    const hipError_t e = launch_plaquette(g, gauge, out, work, static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_plaquette");
+    const hipError_t e = launch_plaquette(g, gauge, packed, out, work,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, packed ? "wl_plaquette_packed" : "wl_plaquette");
+}
+
+int wl_plaquette(const void *gauge, const int32_t dims[4], double *out, void *work,
+                 size_t work_bytes, void *stream) {
+    return plaquette_common(gauge, false, dims, out, work, work_bytes, stream);
+}
+
+int wl_plaquette_packed(const void *gauge, const int32_t dims[4], double *out, void *work,
+                        size_t work_bytes, void *stream) {
+    return plaquette_common(gauge, true, dims, out, work, work_bytes, stream);
 }
 
 int wl_stream_copy(const void *src, void *dst, size_t bytes, void *stream) {

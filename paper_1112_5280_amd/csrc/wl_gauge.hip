@@ -59,18 +59,40 @@ __device__ __forceinline__ void unif4(uint32_t a, uint32_t b, uint32_t c, uint32
 constexpr int kHbTries = 128;
 
 struct GaugeArgs {
-    double2 *U;          // [V][4][9] complex
+    double2 *U;          // canonical [V][4][9] complex, or the packed FP64 field
     int L[4];
     int V;
     int mu, par;
     double beta;
     uint32_t sweep, k0, k1;
+    size_t S;            // packed: sites per parity block (Vh rounded up)
 };
 
-__device__ __forceinline__ void ld(const double2 *U, int s, int mu, C m[9]) {
-    const double2 *p = U + (size_t(s) * 4 + mu) * 9;
+// Link U_mu at lexicographic site s with coordinates c. Canonical: its 9
+// complex numbers are contiguous. Packed (the FP64 18-real layout of
+// wl_pack_gauge): entry k of the links of parity p and direction mu is an
+// array of S complex numbers indexed by the checkerboard index s / 2, so
+// neighbouring threads read neighbouring addresses.
+template <bool PACKED>
+__device__ __forceinline__ const double2 *link_at(const double2 *U, size_t S, int s,
+                                                  const int c[4], int mu, size_t *stride) {
+    if constexpr (PACKED) {
+        const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
+        *stride = S;
+        return U + size_t(par * 4 + mu) * 9 * S + (s >> 1);
+    } else {
+        *stride = 1;
+        return U + (size_t(s) * 4 + mu) * 9;
+    }
+}
+
+template <bool PACKED>
+__device__ __forceinline__ void ld(const double2 *U, size_t S, int s, const int c[4], int mu,
+                                   C m[9]) {
+    size_t st;
+    const double2 *p = link_at<PACKED>(U, S, s, c, mu, &st);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) m[k] = {p[k].x, p[k].y};
+    for (int k = 0; k < 9; ++k) m[k] = {p[k * st].x, p[k * st].y};
 }
 
 // c = a b, a b^dag, a^dag b
@@ -101,6 +123,7 @@ __device__ __forceinline__ int site_of(const int L[4], const int c[4]) {
     return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]));
 }
 
+template <bool PACKED>
 __global__ void __launch_bounds__(kBlock) heatbath_kernel(GaugeArgs a) {
     const int i = blockIdx.x * kBlock + threadIdx.x;   // index among the sites of parity par
     if (i >= a.V / 2) return;
@@ -130,26 +153,27 @@ __global__ void __launch_bounds__(kBlock) heatbath_kernel(GaugeArgs a) {
         int g[4] = {c[0], c[1], c[2], c[3]};
         g[nu] = (c[nu] - 1 + a.L[nu]) % a.L[nu];
         const int xmnu = site_of(a.L, g);
-        g[mu] = (g[mu] + 1) % a.L[mu];
-        const int xpmu_mnu = site_of(a.L, g);
+        int h[4] = {g[0], g[1], g[2], g[3]};
+        h[mu] = (h[mu] + 1) % a.L[mu];
+        const int xpmu_mnu = site_of(a.L, h);
         C m1[9], m2[9], t[9];
-        ld(a.U, xpmu, nu, m1);     // U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
-        ld(a.U, xpnu, mu, m2);
+        ld<PACKED>(a.U, a.S, xpmu, e, nu, m1);     // U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+        ld<PACKED>(a.U, a.S, xpnu, f, mu, m2);
         mmd(m1, m2, t);
-        ld(a.U, s, nu, m1);
+        ld<PACKED>(a.U, a.S, s, c, nu, m1);
         mmd(t, m1, m2);
 #pragma unroll
         for (int k = 0; k < 9; ++k) A[k] = A[k] + m2[k];
-        ld(a.U, xmnu, mu, m1);     // (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu)
-        ld(a.U, xpmu_mnu, nu, m2);
+        ld<PACKED>(a.U, a.S, xmnu, g, mu, m1);     // (U_mu(x-nu) U_nu(x+mu-nu))^dag U_nu(x-nu)
+        ld<PACKED>(a.U, a.S, xpmu_mnu, h, nu, m2);
         mm(m1, m2, t);
-        ld(a.U, xmnu, nu, m1);
+        ld<PACKED>(a.U, a.S, xmnu, g, nu, m1);
         mdm(t, m1, m2);
 #pragma unroll
         for (int k = 0; k < 9; ++k) A[k] = A[k] + m2[k];
     }
     C u[9];
-    ld(a.U, s, mu, u);
+    ld<PACKED>(a.U, a.S, s, c, mu, u);
     constexpr int sub[3][2] = {{0, 1}, {1, 2}, {0, 2}};
 #pragma unroll
     for (int gidx = 0; gidx < 3; ++gidx) {
@@ -201,25 +225,42 @@ __global__ void __launch_bounds__(kBlock) heatbath_kernel(GaugeArgs a) {
             u[3 * jj + col] = rr[2] * ui + rr[3] * uj;
         }
     }
-    double2 *p = a.U + (size_t(s) * 4 + mu) * 9;
+    size_t st;
+    double2 *p = const_cast<double2 *>(link_at<PACKED>(a.U, a.S, s, c, mu, &st));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) p[k] = double2{u[k].re, u[k].im};
+    for (int k = 0; k < 9; ++k) p[k * st] = double2{u[k].re, u[k].im};
 }
 
 // Sum over a block's sites of sum_{mu < nu} Re Tr U_mu nu(x) / 3; one partial per block.
+// Canonical: thread n takes lexicographic site n; packed: the sites of parity
+// n / Vh in checkerboard order (coalesced loads of the packed field).
+template <bool PACKED>
 __global__ void __launch_bounds__(kBlock) plaquette_kernel(const double2 *U, Geom g,
                                                            double *partials) {
     const int V = 2 * g.Vh;
-    const int s = blockIdx.x * kBlock + threadIdx.x;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
     double sum[1] = {0.0};
-    if (s < V) {
+    if (n < V) {
         int c[4];
-        int r = s;
+        if constexpr (PACKED) {
+            const int par = n >= g.Vh ? 1 : 0;
+            const int i = n - par * g.Vh;
+            const int xh = i % g.Lxh;
+            int r = i / g.Lxh;
+            c[1] = r % g.L[1];
+            r /= g.L[1];
+            c[2] = r % g.L[2];
+            c[3] = r / g.L[2];
+            c[0] = 2 * xh + ((c[1] + c[2] + c[3] + par) & 1);
+        } else {
+            int r = n;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            c[m] = r % g.L[m];
-            r /= g.L[m];
+            for (int m = 0; m < 4; ++m) {
+                c[m] = r % g.L[m];
+                r /= g.L[m];
+            }
         }
+        const int s = site_of(g.L, c);
         for (int mu = 0; mu < 4; ++mu)
             for (int nu = mu + 1; nu < 4; ++nu) {
                 int e[4] = {c[0], c[1], c[2], c[3]};
@@ -227,12 +268,13 @@ __global__ void __launch_bounds__(kBlock) plaquette_kernel(const double2 *U, Geo
                 int f[4] = {c[0], c[1], c[2], c[3]};
                 f[nu] = (c[nu] + 1) % g.L[nu];
                 C m1[9], m2[9], t[9];
-                ld(U, s, mu, m1);                 // U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
-                ld(U, site_of(g.L, e), nu, m2);
+                const size_t S = g.S;
+                ld<PACKED>(U, S, s, c, mu, m1);   // U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+                ld<PACKED>(U, S, site_of(g.L, e), e, nu, m2);
                 mm(m1, m2, t);
-                ld(U, site_of(g.L, f), mu, m1);
+                ld<PACKED>(U, S, site_of(g.L, f), f, mu, m1);
                 mmd(t, m1, m2);
-                ld(U, s, nu, m1);
+                ld<PACKED>(U, S, s, c, nu, m1);
                 double tr = 0.0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
@@ -257,15 +299,16 @@ __global__ void __launch_bounds__(kBlock) plaquette_finish(const double *partial
 
 }  // namespace
 
-hipError_t launch_heatbath(const Geom &g, void *canon, double beta, int nsweeps,
+hipError_t launch_heatbath(const Geom &g, void *field, bool packed, double beta, int nsweeps,
                            uint32_t sweep0, uint32_t seed, hipStream_t s) {
     GaugeArgs a;
-    a.U = static_cast<double2 *>(canon);
+    a.U = static_cast<double2 *>(field);
     for (int m = 0; m < 4; ++m) a.L[m] = g.L[m];
     a.V = 2 * g.Vh;
     a.beta = beta;
     a.k0 = seed;
     a.k1 = 0x68656174u;
+    a.S = size_t(g.S);
     const int nb = (g.Vh + kBlock - 1) / kBlock;
     for (int n = 0; n < nsweeps; ++n)
         for (int mu = 0; mu < 4; ++mu)
@@ -273,7 +316,10 @@ hipError_t launch_heatbath(const Geom &g, void *canon, double beta, int nsweeps,
                 a.mu = mu;
                 a.par = par;
                 a.sweep = sweep0 + uint32_t(n);
-                hipLaunchKernelGGL(heatbath_kernel, dim3(nb), dim3(kBlock), 0, s, a);
+                if (packed)
+                    hipLaunchKernelGGL(heatbath_kernel<true>, dim3(nb), dim3(kBlock), 0, s, a);
+                else
+                    hipLaunchKernelGGL(heatbath_kernel<false>, dim3(nb), dim3(kBlock), 0, s, a);
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
@@ -284,11 +330,15 @@ size_t plaquette_workspace_bytes(const Geom &g) {
     return sizeof(double) * size_t((2 * g.Vh + kBlock - 1) / kBlock);
 }
 
-hipError_t launch_plaquette(const Geom &g, const void *canon, double *out, void *work,
-                            hipStream_t s) {
+hipError_t launch_plaquette(const Geom &g, const void *field, bool packed, double *out,
+                            void *work, hipStream_t s) {
     const int nb = (2 * g.Vh + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(plaquette_kernel, dim3(nb), dim3(kBlock), 0, s,
-                       static_cast<const double2 *>(canon), g, static_cast<double *>(work));
+    if (packed)
+        hipLaunchKernelGGL(plaquette_kernel<true>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double2 *>(field), g, static_cast<double *>(work));
+    else
+        hipLaunchKernelGGL(plaquette_kernel<false>, dim3(nb), dim3(kBlock), 0, s,
+                           static_cast<const double2 *>(field), g, static_cast<double *>(work));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(plaquette_finish, dim3(1), dim3(kBlock), 0, s,

@@ -51,7 +51,8 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "wl_server_pending", "wl_server_destroy", "wl_tuning_report", "wl_stream_copy",
            "solve_cg_noalloc", "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
            "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators",
-           "wl_heatbath", "wl_plaquette_workspace_bytes", "wl_plaquette")
+           "wl_heatbath", "wl_plaquette_workspace_bytes", "wl_plaquette",
+           "wl_heatbath_packed", "wl_plaquette_packed")
 
 
 class WilsonError(RuntimeError):
@@ -121,12 +122,14 @@ def _load():
     for f in (lib.solve_cg_tm, lib.solve_bicgstab_tm):
         f.argtypes = [P, P, P, P, D, D, P, D, I32, U32, P, SZ, ctypes.POINTER(SolveStats), P]
         f.restype = ctypes.c_int
-    lib.wl_heatbath.argtypes = [P, P, D, I32, U32, U32, P]
-    lib.wl_heatbath.restype = ctypes.c_int
+    for f in (lib.wl_heatbath, lib.wl_heatbath_packed):
+        f.argtypes = [P, P, D, I32, U32, U32, P]
+        f.restype = ctypes.c_int
     lib.wl_plaquette_workspace_bytes.argtypes = [P]
     lib.wl_plaquette_workspace_bytes.restype = SZ
-    lib.wl_plaquette.argtypes = [P, P, P, P, SZ, P]
-    lib.wl_plaquette.restype = ctypes.c_int
+    for f in (lib.wl_plaquette, lib.wl_plaquette_packed):
+        f.argtypes = [P, P, P, P, SZ, P]
+        f.restype = ctypes.c_int
     lib.wl_meson_workspace_bytes.argtypes = [P]
     lib.wl_meson_workspace_bytes.restype = SZ
     lib.wl_meson_correlators.argtypes = [P, P, I32, P, P, SZ, P]
@@ -424,11 +427,36 @@ def heatbath(U, dims, beta, nsweeps=1, sweep0=0, seed=0, stream=None):
 
 def plaquette(U, dims, stream=None):
     """Mean plaquette of the canonical complex128 device field U[V, 4, 3, 3]."""
-    out = torch.empty(1, dtype=torch.float64, device=U.device)
+    return _plaquette(lib.wl_plaquette, "wl_plaquette", U, dims, stream)
+
+
+def _packed_field(G, dims):
+    if (not isinstance(G, torch.Tensor) or G.dtype != torch.uint8 or not G.is_contiguous()
+            or G.numel() != gauge_bytes(dims, F64)):
+        raise ValueError("G must be the packed FP64 18-real field (pack_gauge(U, dims, F64))")
+
+
+def heatbath_packed(G, dims, beta, nsweeps=1, sweep0=0, seed=0, stream=None):
+    """heatbath on the packed FP64 18-real field G (pack_gauge(U, dims)): the
+    same update as heatbath on U, with coalesced loads; asynchronous."""
+    _packed_field(G, dims)
+    _check(lib.wl_heatbath_packed(_ptr(G), _dims(dims), float(beta), int(nsweeps),
+                                  int(sweep0) & 0xffffffff, int(seed) & 0xffffffff,
+                                  _stream(stream)), "wl_heatbath_packed")
+
+
+def plaquette_packed(G, dims, stream=None):
+    """Mean plaquette of the packed FP64 18-real field G."""
+    _packed_field(G, dims)
+    return _plaquette(lib.wl_plaquette_packed, "wl_plaquette_packed", G, dims, stream)
+
+
+def _plaquette(fn, name, field, dims, stream):
+    out = torch.empty(1, dtype=torch.float64, device=field.device)
     work = torch.empty(max(int(lib.wl_plaquette_workspace_bytes(_dims(dims))), 8),
-                       dtype=torch.uint8, device=U.device)
-    _check(lib.wl_plaquette(_ptr(U), _dims(dims), _ptr(out), _ptr(work), work.numel(),
-                            _stream(stream, out, work)), "wl_plaquette")
+                       dtype=torch.uint8, device=field.device)
+    _check(fn(_ptr(field), _dims(dims), _ptr(out), _ptr(work), work.numel(),
+              _stream(stream, out, work)), name)
     (torch.cuda.current_stream() if stream is None else stream).synchronize()
     return float(out.cpu())
 

@@ -103,3 +103,48 @@ def test_thermalised_fields_and_solves(w):
     assert st["status"] == 0
     x = gu.to_np(w.unpack_spinor(X, dims))
     assert oracle.true_residual(U, b, x, dims, 0.155) <= 1e-10
+
+
+@pytest.mark.parametrize("dims,beta", [((4, 4, 4, 8), 5.7), ((6, 4, 6, 10), 2.0),
+                                       ((4, 6, 4, 4), 0.5)],
+                         ids=["4^3x8-b5.7", "6x4x6x10-b2.0", "4x6x4x4-b0.5"])
+def test_heatbath_packed_is_the_canonical_heatbath(w, dims, beta):
+    """The heat bath on the packed FP64 field does the canonical kernel's
+    arithmetic on the same links with the same draws: packing the canonical
+    result gives bitwise the packed result (6x4x6x10 has Vh = 720 sites per
+    parity in blocks of S = 768, so the padding is covered too); the packed
+    plaquette is the canonical one up to its summation order."""
+    U0 = synth.gauge_haar(dims, 21)
+    Ud = torch.from_numpy(U0.copy()).to("cuda")
+    G = w.pack_gauge(U0, dims)
+    w.heatbath(Ud, dims, beta, nsweeps=2, sweep0=3, seed=7)
+    w.heatbath_packed(G, dims, beta, nsweeps=2, sweep0=3, seed=7)
+    gu.sync()
+    # the packed field: 2 parities x 4 directions x 9 entries, each an array of
+    # S complex numbers of which the first Vh are sites (the rest is padding
+    # that pack_gauge does not write and no kernel reads)
+    vh = int(np.prod(dims)) // 2
+    S = G.numel() // (72 * 16)
+
+    def sites(t):
+        return torch.view_as_real(t.view(torch.complex128).view(72, S)[:, :vh])
+    assert torch.equal(sites(G), sites(w.pack_gauge(Ud, dims)))
+    p, pp = w.plaquette(Ud, dims), w.plaquette_packed(G, dims)
+    assert abs(pp - p) <= 1e-14 * abs(p), (p, pp)
+    # and the oracle's plaquette of the same links
+    assert abs(pp - oracle.plaquette(gu.to_np(Ud), dims)) <= 1e-13
+
+
+def test_packed_gauge_argument_errors(w):
+    dims = (4, 4, 4, 4)
+    G = w.pack_gauge(synth.gauge_haar(dims, 1), dims)
+    with pytest.raises(ValueError):
+        w.heatbath_packed(G[:-16], dims, 5.7)
+    with pytest.raises(ValueError):
+        w.plaquette_packed(w.pack_gauge(synth.gauge_haar(dims, 1), dims, w.F32), dims)
+    with pytest.raises(w.WilsonError):
+        w.heatbath_packed(G, dims, -1.0)
+    assert w.lib.wl_heatbath_packed(None, w._dims(dims), 5.7, 1, 0, 0, None) == -1
+    unit = np.zeros((256, 4, 3, 3), dtype=np.complex128)
+    unit[..., 0, 0] = unit[..., 1, 1] = unit[..., 2, 2] = 1.0
+    assert abs(w.plaquette_packed(w.pack_gauge(unit, dims), dims) - 1.0) <= 1e-15
