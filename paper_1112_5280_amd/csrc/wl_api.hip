@@ -639,8 +639,8 @@ static int heatbath_common(void *gauge, bool packed, const int32_t dims[4], doub
     if (!gauge) return fail(WL_EINVAL, "NULL buffer");
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(WL_EINVAL, "beta must be positive");
     if (nsweeps < 0) return fail(WL_EINVAL, "nsweeps must be >= 0");
-    const hipError_t e = launch_heatbath(g, gauge, packed, beta, nsweeps, sweep0, seed,
-                                         static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_heatbath_field(g, gauge, packed, beta, nsweeps, sweep0, seed,
+                                               static_cast<hipStream_t>(stream));
     return e == hipSuccess ? WL_OK : hip_fail(e, packed ? "wl_heatbath_packed" : "wl_heatbath");
 }
 
@@ -671,8 +671,8 @@ static int plaquette_common(const void *gauge, bool packed, const int32_t dims[4
     if (work_bytes < need)
         return fail(WL_EWORKSPACE, "workspace too small: need " + std::to_string(need) +
                                        " bytes, got " + std::to_string(work_bytes));
-    const hipError_t e = launch_plaquette(g, gauge, packed, out, work,
-                                          static_cast<hipStream_t>(stream));
+    const hipError_t e = launch_plaquette_field(g, gauge, packed, out, work,
+                                                static_cast<hipStream_t>(stream));
     return e == hipSuccess ? WL_OK : hip_fail(e, packed ? "wl_plaquette_packed" : "wl_plaquette");
 }
 

@@ -299,8 +299,8 @@ __global__ void __launch_bounds__(kBlock) plaquette_finish(const double *partial
 
 }  // namespace
 
-hipError_t launch_heatbath(const Geom &g, void *field, bool packed, double beta, int nsweeps,
-                           uint32_t sweep0, uint32_t seed, hipStream_t s) {
+hipError_t launch_heatbath_field(const Geom &g, void *field, bool packed, double beta,
+                                 int nsweeps, uint32_t sweep0, uint32_t seed, hipStream_t s) {
     GaugeArgs a;
     a.U = static_cast<double2 *>(field);
     for (int m = 0; m < 4; ++m) a.L[m] = g.L[m];
@@ -330,8 +330,8 @@ size_t plaquette_workspace_bytes(const Geom &g) {
     return sizeof(double) * size_t((2 * g.Vh + kBlock - 1) / kBlock);
 }
 
-hipError_t launch_plaquette(const Geom &g, const void *field, bool packed, double *out,
-                            void *work, hipStream_t s) {
+hipError_t launch_plaquette_field(const Geom &g, const void *field, bool packed, double *out,
+                                  void *work, hipStream_t s) {
     const int nb = (2 * g.Vh + kBlock - 1) / kBlock;
     if (packed)
         hipLaunchKernelGGL(plaquette_kernel<true>, dim3(nb), dim3(kBlock), 0, s,
@@ -344,6 +344,16 @@ hipError_t launch_plaquette(const Geom &g, const void *field, bool packed, doubl
     hipLaunchKernelGGL(plaquette_finish, dim3(1), dim3(kBlock), 0, s,
                        static_cast<const double *>(work), nb, 1.0 / (6.0 * 2 * g.Vh), out);
     return hipGetLastError();
+}
+
+hipError_t launch_heatbath(const Geom &g, void *canon, double beta, int nsweeps,
+                           uint32_t sweep0, uint32_t seed, hipStream_t s) {
+    return launch_heatbath_field(g, canon, false, beta, nsweeps, sweep0, seed, s);
+}
+
+hipError_t launch_plaquette(const Geom &g, const void *canon, double *out, void *work,
+                            hipStream_t s) {
+    return launch_plaquette_field(g, canon, false, out, work, s);
 }
 
 }  // namespace wl

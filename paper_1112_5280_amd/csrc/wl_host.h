@@ -16,6 +16,13 @@ struct TuningSuspended {
     TuningSuspended &operator=(const TuningSuspended &) = delete;
 };
 
+// ---- pure gauge (wl_gauge.hip): the canonical complex128 field, or (packed)
+// the packed FP64 18-real field --------------------------------------------
+hipError_t launch_heatbath_field(const Geom &g, void *field, bool packed, double beta,
+                                 int nsweeps, uint32_t sweep0, uint32_t seed, hipStream_t s);
+hipError_t launch_plaquette_field(const Geom &g, const void *field, bool packed, double *out,
+                                  void *work, hipStream_t s);
+
 // ---- solvers ---------------------------------------------------------------
 size_t workspace_bytes(const Geom &g, uint32_t flags);
 

@@ -377,13 +377,12 @@ size_t meson_workspace_bytes(const Geom &g);
 hipError_t launch_meson(const Geom &g, const void *props, int t0, double *corr, void *work,
                         hipStream_t s);
 
-// Pure-gauge kernels (wl_gauge.hip) on the canonical complex128 field or
-// (packed) on the packed FP64 18-real field
-hipError_t launch_heatbath(const Geom &g, void *field, bool packed, double beta, int nsweeps,
+// Pure-gauge kernels (wl_gauge.hip) on the canonical complex128 field
+hipError_t launch_heatbath(const Geom &g, void *canon, double beta, int nsweeps,
                            uint32_t sweep0, uint32_t seed, hipStream_t s);
 size_t plaquette_workspace_bytes(const Geom &g);
-hipError_t launch_plaquette(const Geom &g, const void *field, bool packed, double *out,
-                            void *work, hipStream_t s);
+hipError_t launch_plaquette(const Geom &g, const void *canon, double *out, void *work,
+                            hipStream_t s);
 
 // Canonical complex128 <-> packed
 hipError_t launch_pack_gauge(const Geom &g, int prec, bool link12, const void *canon,

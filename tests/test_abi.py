@@ -210,3 +210,20 @@ def test_canonical_workspace(w):
                 w.spinor_bytes(d)
             assert canon == want, (d, f)
         assert w.workspace_bytes(d, w.EO | w.CANON, 3) == 0
+
+
+def test_profiled_traffic_matches_the_kernel_sources():
+    """The HBM traffic the benchmark reports comes from committed counter runs
+    of the hopping kernels; it is valid only for the sources those runs
+    measured, which the profile records by hash. A change to those sources
+    must come with new counter runs."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_for_hash", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(os.path.join(root, "profiles", "hop_f32_eo_32x64_pmc.json")) as f:
+        prof = json.load(f)
+    assert prof["source_hash"] == bench.kernel_source_hash()
+    assert bench.profiled_traffic(False) and bench.profiled_traffic(False, fp64=True)
