@@ -146,6 +146,12 @@ size_t wl_gauge_bytes(const int32_t dims[4], uint32_t flags);
  * `flags`. Asynchronous on `stream`. */
 int wl_pack_gauge(const void *canon, void *packed, const int32_t dims[4],
                   uint32_t flags, void *stream);
+/* Packed -> canonical: the inverse of wl_pack_gauge (FP64 18-real exactly; a
+ * 12-real field gets its third rows rebuilt as conj(row0 x row1); FP32 and
+ * FP16 values widened to FP64), e.g. to store a configuration the packed heat
+ * bath produced. Asynchronous on `stream`. */
+int wl_unpack_gauge(const void *packed, void *canon, const int32_t dims[4],
+                    uint32_t flags, void *stream);
 
 /* Canonical complex128 psi[V][4][3] <-> packed full spinor in the precision of
  * `flags`. Asynchronous on `stream`. */

@@ -148,6 +148,19 @@ int wl_pack_spinor(const void *canon, void *packed, const int32_t dims[4], uint3
     return e == hipSuccess ? WL_OK : hip_fail(e, "wl_pack_spinor");
 }
 
+int wl_unpack_gauge(const void *packed, void *canon, const int32_t dims[4], uint32_t flags,
+                    void *stream) {
+    Geom g;
+    std::string why;
+    int prec;
+    if (!make_geom(dims, &g, &why) || !get_prec(flags, &prec, &why)) return fail(WL_EINVAL, why);
+    if (!canon || !packed) return fail(WL_EINVAL, "NULL buffer");
+    if (canon == packed) return fail(WL_EINVAL, "canon and packed alias");
+    const hipError_t e = launch_unpack_gauge(g, prec, flags & WL_LINK12, packed, canon,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WL_OK : hip_fail(e, "wl_unpack_gauge");
+}
+
 int wl_unpack_spinor(const void *packed, void *canon, const int32_t dims[4], uint32_t flags,
                      void *stream) {
     Geom g;

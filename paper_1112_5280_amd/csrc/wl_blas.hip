@@ -355,6 +355,27 @@ __global__ void __launch_bounds__(kBlock) pack_gauge_kernel(Geom g, const double
     store_link_raw<ST, NCL>(packed, g.S, m.par, mu, m.cb, u);
 }
 
+// packed -> canonical link (the inverse of pack_gauge_kernel; a 12-real link
+// gets its third row rebuilt as conj(row0 x row1), as the hopping kernels do)
+template <typename ST, int NCL>
+__global__ void __launch_bounds__(kBlock) unpack_gauge_kernel(Geom g, const void *packed,
+                                                              double2 *canon) {
+    using R = Real<ST>;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;   // = 4 s + mu
+    if (gid >= 8 * g.Vh) return;
+    const int s = gid >> 2, mu = gid & 3;
+    const SiteMap m = site_map(g, s);
+    cpx<R> u[9];
+    load_link_raw<ST, NCL>(packed, g.S, m.par, mu, m.cb, u);
+    if constexpr (NCL == 6) {
+        u[6] = cconj(u[1] * u[5] - u[2] * u[4]);
+        u[7] = cconj(u[2] * u[3] - u[0] * u[5]);
+        u[8] = cconj(u[0] * u[4] - u[1] * u[3]);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) canon[gid * 9 + k] = double2{double(u[k].re), double(u[k].im)};
+}
+
 template <typename ST>
 __global__ void __launch_bounds__(kBlock) pack_spinor_kernel(Geom g, const double2 *canon,
                                                              void *packed, size_t blk) {
@@ -441,6 +462,19 @@ hipError_t launch_pack_gauge(const Geom &g, int prec, bool link12, const void *c
         using ST = decltype(tag);
         if (link12) hipLaunchKernelGGL((pack_gauge_kernel<ST, 6>), grid, block, 0, s, g, c, packed);
         else hipLaunchKernelGGL((pack_gauge_kernel<ST, 9>), grid, block, 0, s, g, c, packed);
+        return 0;
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_gauge(const Geom &g, int prec, bool link12, const void *packed,
+                               void *canon, hipStream_t s) {
+    const dim3 grid(cdiv(8L * g.Vh, kBlock)), block(kBlock);
+    double2 *c = static_cast<double2 *>(canon);
+    with_storage(prec, [&](auto tag) {
+        using ST = decltype(tag);
+        if (link12) hipLaunchKernelGGL((unpack_gauge_kernel<ST, 6>), grid, block, 0, s, g, packed, c);
+        else hipLaunchKernelGGL((unpack_gauge_kernel<ST, 9>), grid, block, 0, s, g, packed, c);
         return 0;
     });
     return hipGetLastError();

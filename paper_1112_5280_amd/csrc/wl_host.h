@@ -16,6 +16,10 @@ struct TuningSuspended {
     TuningSuspended &operator=(const TuningSuspended &) = delete;
 };
 
+// packed -> canonical complex128 gauge field (wl_blas.hip)
+hipError_t launch_unpack_gauge(const Geom &g, int prec, bool link12, const void *packed,
+                               void *canon, hipStream_t s);
+
 // ---- pure gauge (wl_gauge.hip): the canonical complex128 field, or (packed)
 // the packed FP64 18-real field --------------------------------------------
 hipError_t launch_heatbath_field(const Geom &g, void *field, bool packed, double beta,

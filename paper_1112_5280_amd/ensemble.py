@@ -4,9 +4,11 @@ next configuration while another measures the current one.
 
 On one MI355X the two tasks are two HIP streams: the heat-bath sweeps that
 turn configuration k into k+1 are enqueued on the generation stream, and the
-measurement of configuration k (pack, the 12 point-source solves of one
+measurement of configuration k (the 12 point-source solves of one
 propagator, the meson correlators of Eq. 1) runs meanwhile on the measurement
-stream. Every step is a library call; this module only orders them (events
+stream. Configurations stay in the packed FP64 layout the solvers read (the
+heat bath on that layout is bitwise the one on the canonical field), so
+nothing is packed between the update and the measurement. Every step is a library call; this module only orders them (events
 between the streams) and holds the buffers. The chain and the measurements do
 not depend on the overlap: the kernels are deterministic and each link's
 random numbers are fixed by (seed, sweep, site, direction)."""
@@ -35,9 +37,8 @@ class Ensemble:
         V = int(np.prod(dims))
         self.t0 = self.site // (dims[0] * dims[1] * dims[2])
         dev = "cuda"
-        U0 = torch.as_tensor(U0, dtype=torch.complex128)
-        self.U = [U0.to(dev).contiguous(), torch.empty_like(U0, device=dev)]
-        self.G = torch.empty(w.gauge_bytes(dims), dtype=torch.uint8, device=dev)
+        G0 = w.pack_gauge(U0, dims)                  # packed FP64 18-real
+        self.G = [G0, torch.empty_like(G0)]
         self.B = w.empty_batch(dims, 12)
         src = torch.zeros((V, 4, 3), dtype=torch.complex128, device=dev)
         for r in range(12):
@@ -57,20 +58,25 @@ class Ensemble:
         self.sweep = 0
         self.stats = []
 
+    @property
+    def U(self):
+        """The two configurations held (k % 2 holds configuration k), as
+        canonical complex128 fields [V, 4, 3, 3] (exact copies)."""
+        return [w.unpack_gauge(g, self.dims) for g in self.G]
+
     def _generate(self, k):
-        """U[(k+1)%2] = heat bath of U[k%2], enqueued on the generation stream."""
-        src, dst = self.U[k % 2], self.U[(k + 1) % 2]
+        """G[(k+1)%2] = heat bath of G[k%2], enqueued on the generation stream."""
+        src, dst = self.G[k % 2], self.G[(k + 1) % 2]
         with torch.cuda.stream(self.gen):
             dst.copy_(src)
-            w.heatbath(dst, self.dims, self.beta, self.sweeps, self.sweep, self.seed,
-                       stream=self.gen)
+            w.heatbath_packed(dst, self.dims, self.beta, self.sweeps, self.sweep, self.seed,
+                              stream=self.gen)
         self.sweep += self.sweeps
 
     def _measure(self, k):
         """Correlators of configuration k on the measurement stream."""
         s = self.meas
-        w.pack_gauge(self.U[k % 2], self.dims, out=self.G, stream=s)
-        code, st = w.solve_cg_batch(self.G, self.B, self.X, 12, self.dims, self.kappa,
+        code, st = w.solve_cg_batch(self.G[k % 2], self.B, self.X, 12, self.dims, self.kappa,
                                     tol=self.tol, maxiter=self.maxiter, flags=self.flags,
                                     work=self.work, stream=s)
         if code != w.OK:
@@ -85,7 +91,7 @@ class Ensemble:
             self.meas.wait_stream(self.gen)      # configuration k is complete
             if self.overlap:
                 # configuration k+1 needs k intact until it has copied it; the
-                # measurement only reads U[k % 2], the sweeps write U[(k+1) % 2]
+                # measurement only reads G[k % 2], the sweeps write G[(k+1) % 2]
                 self._generate(k)
                 corr = self._measure(k)
             else:
@@ -94,7 +100,7 @@ class Ensemble:
             ready.record(self.meas)
             ready.synchronize()
             out.append(corr.cpu())
-            # the next generation overwrites U[k % 2]: wait for this measurement
+            # the next generation overwrites G[k % 2]: wait for this measurement
             self.gen.wait_stream(self.meas)
         self.gen.synchronize()
         return torch.stack(out)

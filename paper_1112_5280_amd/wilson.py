@@ -52,7 +52,7 @@ SYMBOLS = ("wl_version", "wl_last_error", "wl_spinor_bytes", "wl_gauge_bytes",
            "solve_cg_noalloc", "wilson_dslash_tm", "wilson_dslash_eo_tm", "solve_cg_tm",
            "solve_bicgstab_tm", "wl_meson_workspace_bytes", "wl_meson_correlators",
            "wl_heatbath", "wl_plaquette_workspace_bytes", "wl_plaquette",
-           "wl_heatbath_packed", "wl_plaquette_packed")
+           "wl_heatbath_packed", "wl_plaquette_packed", "wl_unpack_gauge")
 
 
 class WilsonError(RuntimeError):
@@ -102,7 +102,7 @@ def _load():
     lib.wl_spinor_bytes.restype = SZ
     lib.wl_gauge_bytes.argtypes = [P, U32]
     lib.wl_gauge_bytes.restype = SZ
-    for f in (lib.wl_pack_gauge, lib.wl_pack_spinor, lib.wl_unpack_spinor):
+    for f in (lib.wl_pack_gauge, lib.wl_pack_spinor, lib.wl_unpack_spinor, lib.wl_unpack_gauge):
         f.argtypes = [P, P, P, U32, P]
         f.restype = ctypes.c_int
     lib.wilson_dslash.argtypes = [P, P, P, P, D, P, U32, P]
@@ -288,6 +288,16 @@ def pack_spinor(psi, dims, flags=F64, out=None, stream=None, device="cuda"):
     _check(lib.wl_pack_spinor(_ptr(pd), _ptr(out), _dims(dims), flags, _stream(stream, pd, out)),
            "wl_pack_spinor")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return out
+
+
+def unpack_gauge(packed, dims, flags=F64, stream=None):
+    """Packed gauge field -> canonical complex128 torch tensor [V,4,3,3] on device
+    (the inverse of pack_gauge; 12-real fields get their third rows rebuilt)."""
+    V = int(np.prod(dims))
+    out = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device=packed.device)
+    _check(lib.wl_unpack_gauge(_ptr(packed), _ptr(out), _dims(dims), flags,
+                               _stream(stream, out)), "wl_unpack_gauge")
     return out
 
 

@@ -135,6 +135,22 @@ def test_pack_roundtrip(w):
     assert (err.reshape(len(psi), -1).max(1) <= smax * 2.0 ** -11 * (1 + 1e-6)).all()
 
 
+def test_gauge_pack_roundtrip(w):
+    """unpack_gauge inverts pack_gauge: FP64 18-real exactly; FP32 to the
+    rounding of the stored values; the 12-real formats give the third row
+    rebuilt from the first two, the same unitary link to rounding (the
+    generated links have det = 1 to ~1e-15), FP16 to a few binary16 ulps."""
+    dims = (6, 4, 6, 10)
+    U = synth.gauge_haar(dims, 8)
+    assert np.array_equal(gu.to_np(w.unpack_gauge(w.pack_gauge(U, dims), dims)), U)
+    got = gu.to_np(w.unpack_gauge(w.pack_gauge(U, dims, w.F32), dims, w.F32))
+    assert np.array_equal(got, U.astype(np.complex64).astype(np.complex128))
+    for flags, tol in ((w.F64 | w.LINK12, 1e-14), (w.F32 | w.LINK12, 3e-7), (w.F16S, 5e-4),
+                       (w.F16S | w.LINK12, 2e-3)):
+        got = gu.to_np(w.unpack_gauge(w.pack_gauge(U, dims, flags), dims, flags))
+        assert np.abs(got - U).max() <= tol, (flags, np.abs(got - U).max())
+
+
 def test_f16_storage_far_below_fp32_normal_range(w):
     """Site magnitudes spread over 10^0 .. 10^-44 (into the FP32 denormals, as
     the far sites of a point-source residual are after a few CG iterations),
