@@ -99,7 +99,7 @@ extern "C" {
  * WL_TUNE_FILE=path     keep the autotuner's choices in this file
  * WL_TUNE_FORCE=n,c,g   impose one launch shape on every hop launch (testing)
  * WL_DELTA_F32=d        reliable-update threshold of FP32-inner mixed CG
- *                       (default 3e-3); WL_DELTA_F16 likewise (default 0.2);
+ *                       (default 1e-4); WL_DELTA_F16 likewise (default 0.2);
  *                       WL_DELTA_BI_F32 / WL_DELTA_BI_F16 for mixed BiCGStab
  *                       (defaults 0.1 / 0.3)
  * WL_TRACE=1            one line per solver pass on stderr
@@ -228,7 +228,7 @@ size_t wl_workspace_bytes(const int32_t dims[4], uint32_t flags, int32_t nrhs);
  * of the solve, as one Krylov sequence with reliable updates: whenever the
  * low-precision residual norm has dropped by a factor delta since the last
  * update, the correction is added to the FP64 solution and the residual is
- * recomputed in FP64 and replaces the low-precision one. delta is 3e-3 (FP32
+ * recomputed in FP64 and replaces the low-precision one. delta is 1e-4 (FP32
  * inner) or 0.2 (FP16) for CG, also updating when the residual has not halved
  * in 300 iterations, and 0.1 / 0.3 for BiCGStab (environment WL_DELTA_F32,
  * WL_DELTA_F16, WL_DELTA_BI_F32, WL_DELTA_BI_F16). A mixed BiCGStab whose

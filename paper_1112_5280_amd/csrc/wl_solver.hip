@@ -508,15 +508,16 @@ struct LoVecs {
 
 // residual reduction between reliable updates, per inner precision
 // (measured on the 32^3 x 64 solve: FP32 inner 0.1 -> 11 updates, 147 ms;
-// 3e-3 -> 5 updates, 137 ms, same 152 iterations. FP16 inner 0.2 -> 15
-// updates, 99 ms; 0.1 -> 11, 93 ms but smaller lattices then stall below the
-// FP16 noise floor; 0.05 adds iterations; 0.02 needs 255.) WL_DELTA_F32 /
-// WL_DELTA_F16 override them.
+// 3e-3 -> 5 updates; 1e-4 -> 4 updates, 1-2 % faster than 3e-3 with the same
+// 152 iterations, and the same iterations on 16^3 x 32, 8^4 and the 12
+// point sources of 24^3 x 48. FP16 inner 0.2 -> 15 updates, 99 ms; 0.1 -> 11,
+// 93 ms but smaller lattices then stall below the FP16 noise floor; 0.05 adds
+// iterations; 0.02 needs 255.) WL_DELTA_F32 / WL_DELTA_F16 override them.
 static double reliable_delta(int prec) {
     const char *v = std::getenv(prec == WL_F16S ? "WL_DELTA_F16" : "WL_DELTA_F32");
     const double d = v ? std::atof(v) : 0.0;
     if (d > 0.0 && d < 1.0) return d;
-    return prec == WL_F16S ? 0.2 : 3e-3;
+    return prec == WL_F16S ? 0.2 : 1e-4;
 }
 
 // An inner loop whose residual has not halved within this many iterations has
