@@ -123,6 +123,31 @@ def time_kernel(fn, n, torch):
     return sum(e0.elapsed_time(e1) for e0, e1 in ev) / 1e3 / n
 
 
+def time_kernel_rot(fns, n, torch):
+    """time_kernel over launches that take fns[0], fns[1], ... in turn: each
+    callable works on its own copy of the fields, and the copies together are
+    larger than the 256 MB Infinity Cache, so a launch finds its operands in
+    HBM rather than left in the cache by the launch before it."""
+    k = [0]
+
+    def step():
+        fns[k[0] % len(fns)]()
+        k[0] += 1
+
+    for f in fns:
+        f()
+    return time_kernel(step, n, torch)
+
+
+# total size of the field copies rotated through when an operator's working
+# set would otherwise stay in the 256 MB Infinity Cache
+ROTATE_BYTES = 600 << 20
+
+
+def rotation_copies(ws_bytes):
+    return max(2, -(-ROTATE_BYTES // ws_bytes))
+
+
 def timed(fn, torch):
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -348,8 +373,9 @@ def small_configs(w, torch, synth, n_launch):
     """The two small configurations. 4^4 (Haar, kappa 0.12, FP64): one M apply
     and a CGNR solve -- latency-bound, reported in microseconds. 16^3 x 32
     (exp(i 0.3 H), kappa 0.15): every operator variant (its working set fits in
-    the 256 MB Infinity Cache, so these rates are cache-resident, not HBM) and
-    BiCGStab on the even-odd system, plain FP64 and mixed."""
+    the 256 MB Infinity Cache, so these rates are cache-resident, not HBM; each
+    is timed again over rotated copies of its fields, from HBM) and BiCGStab on
+    the even-odd system, plain FP64 and mixed."""
     s = torch.cuda.current_stream()
     out = {}
     dims, kappa = (4, 4, 4, 4), 0.12
@@ -372,7 +398,7 @@ def small_configs(w, torch, synth, n_launch):
     V = synth.volume(dims)
     U = synth.gauge_smooth(dims, 0.30, 0)
     b = synth.gaussian_spinor(dims, 1)
-    ops = {}
+    ops, hbm = {}, {}
     for prec, pname in ((w.F64, "f64"), (w.F32, "f32")):
         for lk, lname in ((w.LINK18, "18"), (w.LINK12, "12")):
             G = w.pack_gauge(U, dims, prec | lk)
@@ -393,6 +419,25 @@ def small_configs(w, torch, synth, n_launch):
             ops["Deo_%s_%s" % (pname, lname)] = {
                 "us": te * 1e6, "GBs": (per + 4 * COMPLEX_BYTES[prec] * (6 if lk else 9)) * V / 2 / te / 1e9,
                 "GFLOPs": 1320 * V / 2 / te / 1e9}
+            # the same launches with their operands in HBM: copies of the fields
+            # rotated so that no launch finds them in the Infinity Cache
+            ws = G.numel() + P.numel() + O.numel() + Oh.numel()
+            nc = rotation_copies(ws)
+            cp = [(G, P, O, Oh)] + [(G.clone(), P.clone(), torch.empty_like(O),
+                                     torch.empty_like(Oh)) for _ in range(nc - 1)]
+            tm = time_kernel_rot([lambda c=c: w.wilson_dslash(c[0], c[1], c[2], dims, kappa,
+                                                              flags=prec | lk, stream=s)
+                                  for c in cp], n_launch, torch)
+            te = time_kernel_rot([lambda c=c: w.wilson_dslash_eo(
+                c[0], w.parity_block(c[1], dims, prec, 0), c[3], dims, kappa, 1,
+                flags=prec | lk | w.HOP, stream=s) for c in cp], n_launch, torch)
+            hbm["M_%s_%s" % (pname, lname)] = {"us": tm * 1e6, "GBs": per * V / tm / 1e9,
+                                               "copies": nc}
+            hbm["Deo_%s_%s" % (pname, lname)] = {
+                "us": te * 1e6,
+                "GBs": (per + 4 * COMPLEX_BYTES[prec] * (6 if lk else 9)) * V / 2 / te / 1e9,
+                "copies": nc}
+            del cp
     G = w.pack_gauge(U, dims)
     B = w.pack_spinor(b, dims)
     X = w.empty_spinor(dims)
@@ -406,7 +451,7 @@ def small_configs(w, torch, synth, n_launch):
                         "fp64_iterations": st["fp64_iterations"], "restarts": st["restarts"],
                         "true_res": st["true_res"]}
     out["16^3x32"] = {"lattice": list(dims), "kappa": kappa, "cache_resident": True,
-                      "operators": ops, "solves": solves}
+                      "operators": ops, "operators_hbm": hbm, "solves": solves}
 
     # one GPU's share of 32^3x64 cut into 8 along t: the 32^3x8 local volume
     # (periodic here; over 8 GPUs its two t faces, one spin-projected half
@@ -432,8 +477,25 @@ def small_configs(w, torch, synth, n_launch):
                                   "GBs": (2 * SPINOR_BYTES[prec] + 4 * lb) * V / tm / 1e9}
         loc["Deo_%s_18" % pname] = {"us": te * 1e6,
                                     "GBs": (2 * SPINOR_BYTES[prec] + 8 * lb) * V / 2 / te / 1e9}
+        # a local volume's fields fit in the Infinity Cache (FP64: 251 MB); the
+        # same launches over rotated copies give the HBM rate
+        ws = G.numel() + P.numel() + O.numel() + Oh.numel()
+        nc = rotation_copies(ws)
+        cp = [(G, P, O, Oh)] + [(G.clone(), P.clone(), torch.empty_like(O), torch.empty_like(Oh))
+                                for _ in range(nc - 1)]
+        tm = time_kernel_rot([lambda c=c: w.wilson_dslash(c[0], c[1], c[2], dims, kappa,
+                                                          flags=prec, stream=s)
+                              for c in cp], n_launch, torch)
+        te = time_kernel_rot([lambda c=c: w.wilson_dslash_eo(
+            c[0], w.parity_block(c[1], dims, prec, 0), c[3], dims, kappa, 1,
+            flags=prec | w.HOP, stream=s) for c in cp], n_launch, torch)
+        loc["M_%s_18_hbm" % pname] = {"us": tm * 1e6, "copies": nc,
+                                      "GBs": (2 * SPINOR_BYTES[prec] + 4 * lb) * V / tm / 1e9}
+        loc["Deo_%s_18_hbm" % pname] = {
+            "us": te * 1e6, "copies": nc,
+            "GBs": (2 * SPINOR_BYTES[prec] + 8 * lb) * V / 2 / te / 1e9}
         loc["face_bytes_%s" % pname] = 6 * COMPLEX_BYTES[prec] * face
-        del G, P, O, Oh
+        del G, P, O, Oh, cp
     out["32^3x8_local_volume"] = loc
     return out
 
