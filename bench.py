@@ -20,7 +20,7 @@ host threads); ``serving`` summarises the served streams. Everything else
 24^3 x 48 propagator and their meson correlators, the uneven batch of 64
 small lattices, the served Poisson streams by size, a twisted-mass solve, the
 heat bath, plaquette and an overlapped configuration chain, the autotuner's
-record) goes to stderr and to gpurun_out/bench_detail.json.
+record) goes to stderr and, as JSON, to the file ``--detail`` names.
 """
 import argparse
 import json
@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file (relative to this script's folder) for the full results")
     ap.add_argument("--serving-merge", type=int, default=8,
                     help="most waiting requests of one size served as one batch")
     return ap.parse_args()
@@ -686,7 +688,7 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots, merge, slacks=(SERVE_S
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
     import numpy as np
@@ -989,8 +991,9 @@ def main():
     }
     # the details go to stderr and to a file; stdout ends with one compact line
     log("detail: " + json.dumps(detail))
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as f:
+    detail_path = os.path.join(ROOT, args.detail)
+    os.makedirs(os.path.dirname(detail_path) or ROOT, exist_ok=True)
+    with open(detail_path, "w") as f:
         json.dump(detail, f, indent=1)
 
     def pick(d, *keys):
@@ -1045,7 +1048,7 @@ def main():
                              "seconds_per_iteration", "seconds_per_apply",
                              "seconds_per_apply_1_core"),
         "serving": serve_sum,
-        "detail_file": "gpurun_out/bench_detail.json",
+        "detail_file": args.detail,
     }
     for k in ("roofline", "roofline_fp64_eo"):
         if out[k]:

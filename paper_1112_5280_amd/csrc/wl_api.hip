@@ -30,7 +30,8 @@ bool make_geom(const int32_t dims[4], Geom *g, std::string *why) {
     }
     // 36 link chunks per parity block must stay addressable with 32-bit offsets
     if (v / 2 * 36 >= (1L << 31) - 64 * 36) {
-        *why = "lattice too large for this build (V = " + std::to_string(v) + ")";
+        *why = "lattice too large: a parity block's link chunks overflow 32-bit offsets (V = " +
+               std::to_string(v) + ")";
         return false;
     }
     g->Lxh = dims[0] / 2;
