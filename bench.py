@@ -639,15 +639,15 @@ def serving(w, torch, synth, np, n_req, budget_gb, slots, merge, slacks=(SERVE_S
            "kappa": [0.12, 0.155], "resident_fields": 8,
            "solver": "eo CG, FP16-storage inner, FP64 reliable updates, tol 1e-10",
            "fp64_solver": "eo CG in FP64, one request at a time, tol 1e-10"}
-    # closed-loop saturation of each server (every request queued at once)
-    sat = run(mixed, slots, None, max(100, n_req // 4), 40, 10, merge)
+    # closed-loop saturation of each server (every request queued at once),
+    # each on exactly the requests of its 0.8 S stream (same count, warm-up
+    # and seed): the requests span 1 ms to a quarter second, so a smaller or
+    # other sample misjudges that stream's capacity and the "0.8" load can
+    # exceed it
+    sat = run(mixed, slots, None, n_req, 41, 20, merge)
     S = sat["solves_per_s"]
     out["closed_loop"] = sat
     out["saturation_solves_per_s"] = S
-    # the FP64 server's closed loop takes exactly the requests of its 0.8 S64
-    # stream (same count, warm-up and seed): its requests span 1 ms to a
-    # quarter second, so a smaller or other sample misjudges that stream's
-    # capacity and the "0.8" load can exceed it
     n64 = max(100, n_req // 2)
     sat64 = run(w.EO, 1, None, n64, 41, 10, 1)
     S64 = sat64["solves_per_s"]
